@@ -1,0 +1,244 @@
+/*
+ * mcwind -- mass-consistent wind downscaling on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libmcwind.so.  The library solves the finite element form of the
+ * problem of Mandel, Farguell, Kochanski, Mallia and Hilburn, "Simple finite
+ * elements and multigrid for efficient mass-consistent wind downscaling in a
+ * coupled fire-atmosphere model":
+ *
+ *   find the wind u closest to u0 in the norm weighted by A = diag(a_d^2)
+ *   subject to div u = 0 in the domain and u.n = 0 on the surface Gamma
+ *   (Sec. 2, eq. (1)),
+ *
+ * through its Lagrange multiplier lambda, which solves the generalized
+ * Poisson problem -div A^-1 grad lambda = div u0 with lambda = 0 on the
+ * boundary outside Gamma (eq. (4)) in the variational form of eq. (5),
+ * discretised by isoparametric trilinear hexahedra (2x2x2 Gauss stiffness,
+ * one-point right-hand side), solved by multigrid with 4-colour vertical
+ * Gauss-Seidel smoothing and variational coarse-grid correction with adaptive
+ * semicoarsening (Sec. 3, eqs. (6)-(7)); the wind is recovered at element
+ * centres as u = u0 + A^-1 grad lambda (eq. (3)).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Grid: nx x ny x nz hexahedral elements on a logically Cartesian grid of
+ *   N = (nx+1)(ny+1)(nz+1) nodes.  Node arrays are x fastest: node (i,j,k) is
+ *   entry i + (nx+1)*(j + (ny+1)*k).  Elements must be right-handed
+ *   (i, j, k increasing along x, y, z), i.e. det J > 0 everywhere.
+ * Element arrays (u0, u, gradients) are structure of arrays (3, nz, ny, nx):
+ *   component d of element (i,j,k) is entry i + nx*(j + ny*(k + nz*d)).
+ * Gamma: bit mask of grid faces where u.n = 0 is imposed (lambda free):
+ *   bit 0 bottom k=0, bit 1 top k=nz, bit 2 x-low i=0, bit 3 x-high i=nx,
+ *   bit 4 y-low j=0, bit 5 y-high j=ny.  lambda = 0 at every node on a face
+ *   outside Gamma (edges shared with Gamma included).  The paper's setting is
+ *   MCW_GAMMA_BOTTOM.
+ * Memory: every array pointer is a DEVICE pointer on the device that was
+ *   current at mcw_create, unless the parameter says "host".  The caller
+ *   owns all arrays; the handle owns its hierarchy, operators and workspace.
+ * Streams: the handle runs all work on the stream given to mcw_create (a
+ *   hipStream_t passed as void*, NULL = default stream).  Entry points return
+ *   after the work is complete unless stated otherwise.
+ * Errors: every call returns an mcw_status; nothing throws across the ABI.
+ *   mcw_last_error() gives a message for the last failing call on the handle
+ *   (or for a failed mcw_create, mcw_last_error(NULL)).
+ * Threads: one host thread at a time per handle.
+ */
+#ifndef MCWIND_H
+#define MCWIND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCW_OK = 0,
+  MCW_INVALID_ARG = 1,    /* null pointer, nx/ny < 2, nz < 1, a_d <= 0 or non-finite, bad option */
+  MCW_BAD_GEOMETRY = 2,   /* det J <= 0 at a Gauss point or centre; message names the element */
+  MCW_SINGULAR = 3,       /* Gamma covers the whole boundary: lambda is defined up to a constant */
+  MCW_NONFINITE = 4,      /* NaN or Inf in the right-hand side or the residual */
+  MCW_NOT_CONVERGED = 5,  /* max_cycles reached; lambda holds the last iterate, info the residual */
+  MCW_OOM = 6,            /* device allocation failed */
+  MCW_HIP_ERROR = 7       /* a HIP runtime call failed; message has hipGetErrorString */
+} mcw_status;
+
+#define MCW_GAMMA_BOTTOM 1u
+#define MCW_GAMMA_TOP 2u
+#define MCW_GAMMA_XLO 4u
+#define MCW_GAMMA_XHI 8u
+#define MCW_GAMMA_YLO 16u
+#define MCW_GAMMA_YHI 32u
+
+typedef enum {
+  MCW_FP64 = 0,        /* all multigrid work in FP64 */
+  MCW_FP32_REFINE = 1  /* FP32 V-cycles inside FP64 iterative refinement */
+} mcw_precision;
+
+typedef enum {
+  /* coupling ratio a3*h3 / (a_h*h_h) of the assembled operator (coefficient a_d^-2) */
+  MCW_COARSEN_OPERATOR = 0,
+  /* the ratio printed in Sec. 3: a_h*h3 / (h_h*a3) */
+  MCW_COARSEN_LITERAL = 1,
+  /* base method of Sec. 3: coarsen every direction by 2 */
+  MCW_COARSEN_FULL = 2
+} mcw_coarsen_rule;
+
+/* Problem statement (Sec. 2): node coordinates, penalties, Gamma. */
+typedef struct {
+  int32_t nx, ny, nz;     /* elements per direction; nx, ny >= 2, nz >= 1 */
+  const double* X;        /* device, N node x-coordinates (copied by mcw_create) */
+  const double* Y;        /* device, N node y-coordinates */
+  const double* Z;        /* device, N node z-coordinates */
+  double a[3];            /* penalty constants a_1, a_2, a_3 > 0 (A = diag(a_d^2)) */
+  uint32_t gamma_faces;   /* MCW_GAMMA_* mask; must not contain all six faces */
+} mcw_grid_desc;
+
+typedef struct {
+  int32_t precision;          /* mcw_precision; default MCW_FP32_REFINE */
+  double rtol;                /* stop when ||f - K lambda||_2 <= rtol ||f||_2 (free nodes); default 1e-8 */
+  int32_t max_cycles;         /* V-cycles per solve before MCW_NOT_CONVERGED; default 200 */
+  int32_t nu_pre, nu_post;    /* Gauss-Seidel sweeps before / after the coarse correction; default 2, 2 */
+  int32_t inner_cycles;       /* FP32 V-cycles per refinement step; 0 = chosen from the measured rate */
+  int32_t coarsen_rule;       /* mcw_coarsen_rule; default MCW_COARSEN_OPERATOR */
+  int32_t coarse_direct_max;  /* largest coarsest-level unknown count (direct solve); default 1024, max 4096 */
+  int32_t use_graph;          /* capture the FP32 V-cycle in a hipGraph and replay it; default 1 */
+  int32_t verbose;            /* print setup and convergence lines to stderr; default 0 */
+} mcw_options;
+
+#define MCW_MAX_LEVELS 24
+#define MCW_HISTORY 64
+
+typedef struct {
+  int32_t outer_steps;            /* FP64 residual evaluations after the start */
+  int32_t cycles;                 /* V-cycles performed */
+  double rel_residual;            /* final ||f - K lambda|| / ||f|| (FP64, free nodes) */
+  double rel_divergence;          /* ||D|| / ||D0||, D the weak divergence of u0 + A^-1 grad lambda */
+  double rho;                     /* mean residual reduction per V-cycle */
+  double f_norm;                  /* ||f||_2 over the free nodes */
+  int32_t n_levels;
+  int32_t level_dims[MCW_MAX_LEVELS][3];
+  int32_t n_history;
+  double history[MCW_HISTORY];    /* relative residual after each outer step (FP64) */
+  float ms_total;                 /* device time of the whole solve */
+  float ms_rhs;                   /* right-hand side assembly */
+  float ms_cycles;                /* V-cycles (incl. casts/updates) */
+  float ms_outer;                 /* FP64 matrix-free residuals */
+  float ms_finish;                /* recovery and divergence check */
+} mcw_info;
+
+typedef struct mcw_handle mcw_handle;
+
+/* Fill o with the defaults listed above. */
+void mcw_default_options(mcw_options* o);
+
+/* Set up a grid (Sec. 2 discretisation, Sec. 3 hierarchy): validates the
+ * arguments, checks det J > 0 at every Gauss point and element centre,
+ * assembles the 27-point fine stiffness stencil from 2x2x2 Gauss quadrature,
+ * chooses the coarse grids by the coarsening rule, forms the Galerkin
+ * operators K_c = P^T K P and factors the coarsest one.  opts may be NULL
+ * (defaults).  stream is a hipStream_t or NULL.  On success *out owns all of
+ * the handle's device memory until mcw_destroy. */
+mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
+                      mcw_handle** out);
+
+void mcw_destroy(mcw_handle* h);
+
+/* Change the stopping tolerance and cycle limit of later solves on h
+ * (rtol in (0,1), max_cycles >= 1); the hierarchy and operators are kept. */
+mcw_status mcw_set_tolerance(mcw_handle* h, double rtol, int32_t max_cycles);
+
+/* Solve for the multiplier and recover the wind.
+ * u0:     device, (3, nz, ny, nx) FP64 initial wind at element centres.
+ * lambda: device, N FP64; on entry the starting guess (warm start from the
+ *         previous time step; zeros = cold start; entries at fixed nodes are
+ *         ignored), on exit the solution with zeros at fixed nodes.
+ * u:      device, (3, nz, ny, nx) FP64 output wind; may be NULL (skips recovery).
+ * info:   host, may be NULL.
+ * Returns MCW_NOT_CONVERGED with lambda = last iterate if rtol is not reached
+ * in max_cycles V-cycles, MCW_NONFINITE if u0 or the iteration is not finite. */
+mcw_status mcw_solve(mcw_handle* h, const double* u0, double* lambda, double* u, mcw_info* info);
+
+/* Solve m independent problems (an ensemble or several time steps), each on
+ * its own handle, advancing them together: every multigrid phase is one
+ * launch over all members that still iterate.  Arrays as in mcw_solve, one
+ * per member (host arrays of device pointers); infos may be NULL or hold m
+ * entries.  All handles must share one device and precision; the stream of
+ * hs[0] is used.  Returns the first non-OK member status. */
+mcw_status mcw_solve_batch(int32_t m, mcw_handle* const* hs, const double* const* u0,
+                           double* const* lambda, double* const* u, mcw_info* infos);
+
+/* Reverse mode through the solve (transpose multigrid solve with the same
+ * symmetric operator plus the adjoints of recovery and right-hand side).
+ * lambda: device N FP64, the solution of mcw_solve for this u0 and handle.
+ * g_u:    device (3, nz, ny, nx) FP64, dL/du at element centres.
+ * dL_du0: device (3, nz, ny, nx) FP32 output.
+ * dL_da:  host double[3] output, dL/da_d.
+ * info:   host, may be NULL (describes the transpose solve). */
+mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, float* dL_du0,
+                       double dL_da[3], mcw_info* info);
+
+/* ---- single-step entry points (each runs one operation of the path) ---- */
+
+/* y = K x with the matrix-free element-by-element apply (2x2x2 Gauss), FP64,
+ * full node vectors, no boundary conditions applied (rows of fixed nodes are
+ * the unconstrained stiffness rows). */
+mcw_status mcw_apply_K(mcw_handle* h, const double* x, double* y);
+
+/* f = right-hand side of eq. (5) by one-point quadrature: f_a = -sum_e
+ * 8 detJ_e(0) (B_e(0)^T u0_e)_a at free nodes, 0 at fixed nodes. */
+mcw_status mcw_rhs(mcw_handle* h, const double* u0, double* f);
+
+/* u = u0 + A^-1 grad lambda at element centres (eq. (3)). */
+mcw_status mcw_recover(mcw_handle* h, const double* u0, const double* lambda, double* u);
+
+/* Weak divergence D of u0 + A^-1 grad lambda (each term with its own
+ * quadrature) at all nodes (0 at fixed nodes), and rel = ||D|| / ||D0|| over
+ * the free nodes, D0 the u0 term (host double, may be NULL). */
+mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda, double* D,
+                          double* rel);
+
+/* Number of levels, and the dimensions of level l (host int32[3]: nx, ny, nz),
+ * whether it coarsens horizontally towards level l+1 (host int32, may be NULL)
+ * and its kept node planes (host int32[nz+1], may be NULL; count written to
+ * *n_keep). */
+int32_t mcw_num_levels(const mcw_handle* h);
+mcw_status mcw_level_info(const mcw_handle* h, int32_t l, int32_t dims[3], int32_t* coarsen_h,
+                          int32_t* keep_z, int32_t* n_keep);
+
+/* Copy the 27-point stencil of level l into out: device, 27 x N_l, entry
+ * o*N_l + n holds K[n, n + offset(o)] with o = (di+1) + 3(dj+1) + 9(dk+1), in
+ * natural node order.  prec = MCW_FP64 gives the FP64 operator (available in
+ * FP64 handles; for FP32_REFINE handles only level 0, recomputed), MCW_FP32_REFINE the
+ * FP32 copy used by the V-cycles (out is then float*). */
+mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out);
+
+/* One or more Gauss-Seidel sweeps (4 colour passes, columns bottom-up) on
+ * level l in the handle's precision of the V-cycle (double* for MCW_FP64
+ * handles, float* for MCW_FP32_REFINE): x in/out, f in, level-sized node vectors. */
+mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t sweeps);
+
+/* r = f - K_l x at free nodes, 0 at fixed nodes (V-cycle precision). */
+mcw_status mcw_residual(mcw_handle* h, int32_t l, const void* x, const void* f, void* r);
+
+/* rc = P_l^T r (level l+1 vector, 0 at fixed coarse nodes). */
+mcw_status mcw_restrict(mcw_handle* h, int32_t l, const void* r, void* rc);
+
+/* x += P_l e (x level l, e level l+1). */
+mcw_status mcw_prolong(mcw_handle* h, int32_t l, const void* e, void* x);
+
+/* e = K_L^-1 r on the coarsest level (V-cycle precision, FP64 arithmetic). */
+mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e);
+
+/* One V-cycle on level 0 with x in/out, f in (V-cycle precision). */
+mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
+
+/* ---- errors ---- */
+const char* mcw_status_string(mcw_status s);
+const char* mcw_last_error(const mcw_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCWIND_H */

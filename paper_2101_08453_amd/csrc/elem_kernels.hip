@@ -1,0 +1,751 @@
+// Element-level kernels of the finite element formulation (Sec. 2 of Mandel
+// et al.): geometry check, stiffness stencil assembly, the matrix-free
+// element-by-element stiffness apply with 2x2x2 Gauss quadrature, the
+// one-point right-hand side -int grad(mu).u0, the weak divergence check,
+// the centre-gradient recovery u = u0 + A^-1 grad(lambda), and the adjoints
+// of the recovery and of the right-hand side.
+//
+// Element geometry without forming shape-function gradients: on the reference
+// cube the trilinear map has d x / d xi_1 = 1/2 * bilinear interpolation, in
+// (xi_2, xi_3), of the four x-directed edge vectors x_{1bc} - x_{0bc} (and
+// likewise for xi_2, xi_3).  At the 2x2x2 Gauss points each Jacobian column
+// therefore takes only four distinct values.  With the Jacobian columns c_m,
+// the rows of J^{-1} are r_m / det J with r_0 = c_1 x c_2, r_1 = c_2 x c_0,
+// r_2 = c_0 x c_1, det J = c_0 . r_0.  For a nodal field v with reference
+// gradient g = grad_xi v, the physical gradient is (sum_m g_m r_m) / det J.
+//
+// Local node a = ax + 2 ay + 4 az sits at reference corner (2ax-1, 2ay-1, 2az-1).
+#include "mcw_internal.hpp"
+
+namespace mcw {
+namespace {
+
+constexpr double GQ = 0.57735026918962576451;  // Gauss abscissa 1/sqrt(3)
+constexpr double WP = 0.5 * (1.0 + GQ);        // 1D linear shape value at the near Gauss point
+constexpr double WM = 0.5 * (1.0 - GQ);        // ... at the far Gauss point
+
+// Bilinear interpolation of four corner values v[b + 2c] (b, c in {0,1}) to
+// the four Gauss points (s1, s2): out[s1 + 2 s2] = sum w(b,s1) w(c,s2) v[b+2c],
+// w(b,s) = WP if b == s else WM.  The weight matrix is symmetric, so the same
+// routine is its own transpose (used to spread Gauss-point values to edges).
+__device__ __forceinline__ void bil4(const double v[4], double out[4]) {
+  const double t00 = WP * v[0] + WM * v[1];
+  const double t10 = WM * v[0] + WP * v[1];
+  const double t01 = WP * v[2] + WM * v[3];
+  const double t11 = WM * v[2] + WP * v[3];
+  out[0] = WP * t00 + WM * t01;
+  out[1] = WP * t10 + WM * t11;
+  out[2] = WM * t00 + WP * t01;
+  out[3] = WM * t10 + WP * t11;
+}
+
+// Differences of a nodal scalar along the edges of direction m, indexed by
+// the pair of the other two local coordinates (in increasing axis order).
+__device__ __forceinline__ void edge_diffs(const double v[8], double e[3][4]) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int b = p & 1, c = p >> 1;
+    e[0][p] = v[1 + 2 * b + 4 * c] - v[0 + 2 * b + 4 * c];  // pair (ay, az)
+    e[1][p] = v[b + 2 + 4 * c] - v[b + 4 * c];              // pair (ax, az)
+    e[2][p] = v[b + 2 * c + 4] - v[b + 2 * c];              // pair (ax, ay)
+  }
+}
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Jacobian columns at the Gauss points: Jg[m][d][pair] for column m,
+// coordinate d, pair index of the two other Gauss coordinates.
+__device__ __forceinline__ void gauss_jacobian(const double xe[3][8], double Jg[3][3][4]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double e[3][4];
+    edge_diffs(xe[d], e);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      double o[4];
+      bil4(e[m], o);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) Jg[m][d][p] = 0.5 * o[p];
+    }
+  }
+}
+
+// Jacobian columns at the element centre: c[m][d] = 1/8 sum of the 4 edges.
+__device__ __forceinline__ void centre_jacobian(const double xe[3][8], double c[3][3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double e[3][4];
+    edge_diffs(xe[d], e);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) c[m][d] = 0.125 * (e[m][0] + e[m][1] + e[m][2] + e[m][3]);
+  }
+}
+
+// Reference gradient of a nodal scalar at the centre.
+__device__ __forceinline__ void centre_ref_grad(const double v[8], double g[3]) {
+  double e[3][4];
+  edge_diffs(v, e);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) g[m] = 0.125 * (e[m][0] + e[m][1] + e[m][2] + e[m][3]);
+}
+
+// Rows r_m of the adjugate and det J from Jacobian columns.
+__device__ __forceinline__ double adjugate(const double c0[3], const double c1[3], const double c2[3],
+                                           double r[3][3]) {
+  cross3(c1, c2, r[0]);
+  cross3(c2, c0, r[1]);
+  cross3(c0, c1, r[2]);
+  return dot3(c0, r[0]);
+}
+
+// Gauss point (sx, sy, sz): pair indices of the three Jacobian columns.
+#define GP_PAIRS(sx, sy, sz) const int p0 = (sy) + 2 * (sz), p1 = (sx) + 2 * (sz), p2 = (sx) + 2 * (sy)
+
+// y += K_e v for one element (2x2x2 Gauss, coefficient diag(c)).
+__device__ __forceinline__ void element_apply(const double Jg[3][3][4], const double v[8],
+                                              const double c[3], double y[8]) {
+  double ev[3][4], G[3][4];
+  edge_diffs(v, ev);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    bil4(ev[m], G[m]);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) G[m][p] *= 0.5;
+  }
+  double Acc[3][4] = {};
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    const int sx = g & 1, sy = (g >> 1) & 1, sz = g >> 2;
+    GP_PAIRS(sx, sy, sz);
+    const double c0[3] = {Jg[0][0][p0], Jg[0][1][p0], Jg[0][2][p0]};
+    const double c1[3] = {Jg[1][0][p1], Jg[1][1][p1], Jg[1][2][p1]};
+    const double c2[3] = {Jg[2][0][p2], Jg[2][1][p2], Jg[2][2][p2]};
+    double r[3][3];
+    const double det = adjugate(c0, c1, c2, r);
+    const double g0 = G[0][p0], g1 = G[1][p1], g2 = G[2][p2];
+    double q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q[d] = c[d] * (g0 * r[0][d] + g1 * r[1][d] + g2 * r[2][d]);
+    const double idet = 1.0 / det;
+    Acc[0][p0] += dot3(r[0], q) * idet;
+    Acc[1][p1] += dot3(r[1], q) * idet;
+    Acc[2][p2] += dot3(r[2], q) * idet;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double B[4];
+    bil4(Acc[m], B);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double t = 0.5 * B[p];
+      const int b = p & 1, cc = p >> 1;
+      if (m == 0) { y[1 + 2 * b + 4 * cc] += t; y[0 + 2 * b + 4 * cc] -= t; }
+      if (m == 1) { y[b + 2 + 4 * cc] += t; y[b + 4 * cc] -= t; }
+      if (m == 2) { y[b + 2 * cc + 4] += t; y[b + 2 * cc] -= t; }
+    }
+  }
+}
+
+// Spread a reference-space vector w (one value per direction, at the centre)
+// to the nodes: y_a += s * sum_m sign_m(a) w_m.
+__device__ __forceinline__ void spread_centre(const double w[3], double s, double y[8]) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double sx = (a & 1) ? 1.0 : -1.0, sy = (a & 2) ? 1.0 : -1.0, sz = (a & 4) ? 1.0 : -1.0;
+    y[a] += s * (sx * w[0] + sy * w[1] + sz * w[2]);
+  }
+}
+
+// f_e: -8 detJ(0) B(0)^T u0 = -sum_m sign_m(a) (r_m . u0).
+__device__ __forceinline__ void element_rhs(const double xe[3][8], const double u0[3], double y[8]) {
+  double cj[3][3], r[3][3];
+  centre_jacobian(xe, cj);
+  (void)adjugate(cj[0], cj[1], cj[2], r);
+  const double w[3] = {dot3(r[0], u0), dot3(r[1], u0), dot3(r[2], u0)};
+  spread_centre(w, -1.0, y);
+}
+
+// g_lambda contribution G_1^T diag(c) g: sum_m sign_m(a)/8 (r_m . diag(c) g) / det.
+__device__ __forceinline__ void element_recover_adjoint(const double xe[3][8], const double g[3],
+                                                        const double c[3], double y[8]) {
+  double cj[3][3], r[3][3];
+  centre_jacobian(xe, cj);
+  const double det = adjugate(cj[0], cj[1], cj[2], r);
+  const double cg[3] = {c[0] * g[0], c[1] * g[1], c[2] * g[2]};
+  const double w[3] = {dot3(r[0], cg), dot3(r[1], cg), dot3(r[2], cg)};
+  spread_centre(w, 0.125 / det, y);
+}
+
+__device__ __forceinline__ size_t node_id(int i, int j, int k, int NX, int NY) {
+  return (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * (size_t)k);
+}
+
+// ---------------------------------------------------------------- geometry check
+
+__global__ __launch_bounds__(256) void geometry_check_kernel(const double* __restrict__ X,
+                                                             const double* __restrict__ Y,
+                                                             const double* __restrict__ Z, int nx,
+                                                             int ny, int nz,
+                                                             unsigned long long* first_bad) {
+  const long long E = (long long)nx * ny * nz;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((long long)nx * ny));
+  const int NX = nx + 1, NY = ny + 1;
+  double xe[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const size_t n = node_id(i + (a & 1), j + ((a >> 1) & 1), k + (a >> 2), NX, NY);
+    xe[0][a] = X[n];
+    xe[1][a] = Y[n];
+    xe[2][a] = Z[n];
+  }
+  double Jg[3][3][4];
+  gauss_jacobian(xe, Jg);
+  bool ok = true;
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    GP_PAIRS(g & 1, (g >> 1) & 1, g >> 2);
+    const double c0[3] = {Jg[0][0][p0], Jg[0][1][p0], Jg[0][2][p0]};
+    const double c1[3] = {Jg[1][0][p1], Jg[1][1][p1], Jg[1][2][p1]};
+    const double c2[3] = {Jg[2][0][p2], Jg[2][1][p2], Jg[2][2][p2]};
+    double r[3][3];
+    const double det = adjugate(c0, c1, c2, r);
+    ok = ok && (det > 0.0);
+  }
+  double cj[3][3], r[3][3];
+  centre_jacobian(xe, cj);
+  const double det0 = adjugate(cj[0], cj[1], cj[2], r);
+  ok = ok && (det0 > 0.0);
+  if (!ok) atomicMin(first_bad, (unsigned long long)e);
+}
+
+// ---------------------------------------------------------------- stencil assembly
+
+// Row-split position of x index i: even indices first, then odd.
+__device__ __forceinline__ int rowpos(int i, int NXe) { return (i & 1) ? NXe + (i >> 1) : (i >> 1); }
+
+// One colour class of elements (parity of i, j, k): elements of a class share
+// no node, so each adds its 8x8 matrix into the node stencils without races.
+__global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict__ X,
+                                                       const double* __restrict__ Y,
+                                                       const double* __restrict__ Z, int nx, int ny,
+                                                       int nz, double c0, double c1, double c2,
+                                                       int pi, int pj, int pk,
+                                                       double* __restrict__ st) {
+  const int mx = (nx - pi + 1) / 2, my = (ny - pj + 1) / 2, mz = (nz - pk + 1) / 2;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long long)mx * my * mz) return;
+  const int i = 2 * (int)(tid % mx) + pi;
+  const int j = 2 * (int)((tid / mx) % my) + pj;
+  const int k = 2 * (int)(tid / ((long long)mx * my)) + pk;
+  const int NX = nx + 1, NY = ny + 1, NXe = (NX + 1) >> 1;
+  const size_t N = (size_t)NX * NY * (nz + 1);
+  double xe[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const size_t n = node_id(i + (a & 1), j + ((a >> 1) & 1), k + (a >> 2), NX, NY);
+    xe[0][a] = X[n];
+    xe[1][a] = Y[n];
+    xe[2][a] = Z[n];
+  }
+  double Jg[3][3][4];
+  gauss_jacobian(xe, Jg);
+  const double c[3] = {c0, c1, c2};
+  // column b of K_e is K_e applied to the b-th unit vector
+#pragma unroll 1
+  for (int b = 0; b < 8; ++b) {
+    double v[8] = {}, y[8] = {};
+    v[b] = 1.0;
+    element_apply(Jg, v, c, y);
+    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+      const int o = (bx - ax + 1) + 3 * (by - ay + 1) + 9 * (bz - az + 1);
+      const size_t row = (size_t)(j + ay) * NX + ((size_t)(k + az) * NX * NY);
+      const size_t idx = (size_t)o * N + row + rowpos(i + ax, NXe);
+      st[idx] += y[a];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- element tiles
+
+enum TileMode { M_APPLY = 0, M_RESID = 1, M_RHS = 2, M_DIV = 3, M_ADJ = 4 };
+
+struct TileArgs {
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const double* v;   // nodal field (apply, residual, divergence)
+  const double* f;   // right-hand side (residual)
+  const double* ue;  // element 3-vectors (rhs, divergence, adjoint scatter)
+  double* out;       // nodal output
+  double* partials;  // [channel][block] sums of squares over the free nodes
+  int nx, ny, nz;
+  double c[3];
+  Faces faces;
+};
+
+constexpr int TE = 16;       // element columns per tile side
+constexpr int TN = TE - 1;   // owned node columns per tile side
+
+// Element loop with deterministic per-node accumulation.  A block owns a
+// TN x TN patch of node columns and evaluates the TE x TE element columns
+// touching it (one element column per thread), marching up the layers.  Each
+// element leaves its 4 lower and 4 upper corner contributions in LDS; the
+// owner of a node then sums, in a fixed order, the lower contributions of the
+// current layer and the upper contributions of the layer below.
+template <int MODE>
+__global__ __launch_bounds__(256) void elem_tile_kernel(TileArgs A) {
+  constexpr int CH = (MODE == M_DIV) ? 2 : 1;
+  constexpr bool NODEV = (MODE == M_APPLY || MODE == M_RESID || MODE == M_DIV);
+  constexpr bool ELEMV = (MODE == M_RHS || MODE == M_DIV || MODE == M_ADJ);
+  constexpr bool GAUSS = NODEV;
+  __shared__ double s_lo[CH][4][256];
+  __shared__ double s_up[2][CH][4][256];
+  __shared__ double s_red[256];
+
+  const int t = threadIdx.x, ex = t % TE, ey = t / TE;
+  const int i0 = blockIdx.x * TN, j0 = blockIdx.y * TN;
+  const int ie = i0 - 1 + ex, je = j0 - 1 + ey;
+  const int nx = A.nx, ny = A.ny, nz = A.nz, NX = nx + 1, NY = ny + 1;
+  const bool ev = ie >= 0 && ie < nx && je >= 0 && je < ny;
+  const bool own = ex >= 1 && ey >= 1 && ie <= nx && je <= ny;
+  const bool colfree = own && !A.faces.x_fixed(ie, NX) && !A.faces.y_fixed(je, NY);
+  const int kf = A.faces.k_first(), kl = A.faces.k_last(nz + 1);
+  const int ic = ev ? ie : 0, jc = ev ? je : 0;
+  const size_t plane = (size_t)NX * NY;
+  const size_t E = (size_t)nx * ny * nz;
+
+  double xl[3][4], vl[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const size_t n = (size_t)(jc + (q >> 1)) * NX + ic + (q & 1);
+    xl[0][q] = A.X[n];
+    xl[1][q] = A.Y[n];
+    xl[2][q] = A.Z[n];
+    if (NODEV) vl[q] = A.v[n];
+  }
+  double acc[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) acc[ch] = 0.0;
+
+  auto node_out = [&](int k, const double s[CH]) {
+    const size_t n = (size_t)k * plane + (size_t)je * NX + ie;
+    const bool fr = colfree && k >= kf && k <= kl;
+    if (MODE == M_APPLY) {
+      A.out[n] = s[0];
+    } else if (MODE == M_RESID) {
+      const double r = fr ? A.f[n] - s[0] : 0.0;
+      A.out[n] = r;
+      acc[0] += r * r;
+    } else {
+      const double o = fr ? s[0] : 0.0;
+      A.out[n] = o;
+      acc[0] += o * o;
+      if (CH == 2) {
+        const double o1 = fr ? s[CH - 1] : 0.0;
+        acc[CH - 1] += o1 * o1;
+      }
+    }
+  };
+
+  for (int k = 0; k < nz; ++k) {
+    double xu[3][4], vu[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t n = (size_t)(k + 1) * plane + (size_t)(jc + (q >> 1)) * NX + ic + (q & 1);
+      xu[0][q] = A.X[n];
+      xu[1][q] = A.Y[n];
+      xu[2][q] = A.Z[n];
+      if (NODEV) vu[q] = A.v[n];
+    }
+    double y[CH][8];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) y[ch][a] = 0.0;
+    if (ev) {
+      double xe[3][8], ve[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          xe[d][q] = xl[d][q];
+          xe[d][q + 4] = xu[d][q];
+        }
+        ve[q] = vl[q];
+        ve[q + 4] = vu[q];
+      }
+      if (GAUSS) {
+        double Jg[3][3][4];
+        gauss_jacobian(xe, Jg);
+        element_apply(Jg, ve, A.c, y[0]);
+      }
+      if (ELEMV) {
+        const size_t e = (size_t)k * nx * ny + (size_t)je * nx + ie;
+        const double u[3] = {A.ue[e], A.ue[E + e], A.ue[2 * E + e]};
+        if (MODE == M_RHS) element_rhs(xe, u, y[0]);
+        if (MODE == M_ADJ) element_recover_adjoint(xe, u, A.c, y[0]);
+        if (MODE == M_DIV) {
+          // D0 = 8 detJ(0) B(0)^T u0, the negative of the right-hand side
+          double tmp[8] = {};
+          element_rhs(xe, u, tmp);
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            y[0][a] -= tmp[a];
+            y[CH - 1][a] = -tmp[a];
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s_lo[ch][q][t] = y[ch][q];
+        s_up[k & 1][ch][q][t] = y[ch][q + 4];
+      }
+    __syncthreads();
+    if (own) {
+      double s[CH];
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        double v = s_lo[ch][3][t - TE - 1] + s_lo[ch][2][t - TE] + s_lo[ch][1][t - 1] + s_lo[ch][0][t];
+        if (k > 0) {
+          const int pb = (k - 1) & 1;
+          v += s_up[pb][ch][3][t - TE - 1] + s_up[pb][ch][2][t - TE] + s_up[pb][ch][1][t - 1] +
+               s_up[pb][ch][0][t];
+        }
+        s[ch] = v;
+      }
+      node_out(k, s);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xl[d][q] = xu[d][q];
+      vl[q] = vu[q];
+    }
+  }
+  if (own) {
+    const int pb = (nz - 1) & 1;
+    double s[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+      s[ch] = s_up[pb][ch][3][t - TE - 1] + s_up[pb][ch][2][t - TE] + s_up[pb][ch][1][t - 1] +
+              s_up[pb][ch][0][t];
+    node_out(nz, s);
+  }
+  if (A.partials) {
+    const int nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      __syncthreads();
+      s_red[t] = acc[ch];
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) s_red[t] += s_red[t + w];
+        __syncthreads();
+      }
+      if (t == 0) A.partials[(size_t)ch * nb + bid] = s_red[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- element-wise kernels
+
+// One thread per element column, marching up: recovery u = u0 + diag(c) grad lambda(0).
+__global__ __launch_bounds__(256) void recover_kernel(const double* __restrict__ X,
+                                                      const double* __restrict__ Y,
+                                                      const double* __restrict__ Z,
+                                                      const double* __restrict__ lam,
+                                                      const double* __restrict__ u0,
+                                                      double* __restrict__ u, int nx, int ny, int nz,
+                                                      double c0, double c1, double c2) {
+  const int ie = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int je = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ie >= nx || je >= ny) return;
+  const int NX = nx + 1, NY = ny + 1;
+  const size_t plane = (size_t)NX * NY, E = (size_t)nx * ny * nz;
+  double xe[3][8], v[8];
+  auto load = [&](int k, int h) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t n = (size_t)k * plane + (size_t)(je + (q >> 1)) * NX + ie + (q & 1);
+      xe[0][q + h] = X[n];
+      xe[1][q + h] = Y[n];
+      xe[2][q + h] = Z[n];
+      v[q + h] = lam[n];
+    }
+  };
+  load(0, 0);
+  const double c[3] = {c0, c1, c2};
+  for (int k = 0; k < nz; ++k) {
+    load(k + 1, 4);
+    double cj[3][3], r[3][3], g[3];
+    centre_jacobian(xe, cj);
+    const double det = adjugate(cj[0], cj[1], cj[2], r);
+    centre_ref_grad(v, g);
+    const double idet = 1.0 / det;
+    const size_t e = (size_t)k * nx * ny + (size_t)je * nx + ie;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double gx = (g[0] * r[0][d] + g[1] * r[1][d] + g[2] * r[2][d]) * idet;
+      u[d * E + e] = u0[d * E + e] + c[d] * gx;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xe[d][q] = xe[d][q + 4];
+      v[q] = v[q + 4];
+    }
+  }
+}
+
+// Adjoint element terms: dL/du0 = g_u - 8 detJ(0) B(0) mu (FP32 out) and the
+// per-block sums of dL/dc_d = sum_e g_u,d (B(0) lambda)_d
+//                             - sum_e sum_g detJ_g (B_g mu)_d (B_g lambda)_d.
+__global__ __launch_bounds__(256) void adjoint_elem_kernel(
+    const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
+    const double* __restrict__ lam, const double* __restrict__ mu, const double* __restrict__ gu,
+    float* __restrict__ dL_du0, double* __restrict__ partials, int nx, int ny, int nz) {
+  __shared__ double s_red[256];
+  const int ie = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int je = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const bool act = ie < nx && je < ny;
+  const int NX = nx + 1, NY = ny + 1;
+  const size_t plane = (size_t)NX * NY, E = (size_t)nx * ny * nz;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    double xe[3][8], vl[8], vm[8];
+    auto load = [&](int k, int h) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t n = (size_t)k * plane + (size_t)(je + (q >> 1)) * NX + ie + (q & 1);
+        xe[0][q + h] = X[n];
+        xe[1][q + h] = Y[n];
+        xe[2][q + h] = Z[n];
+        vl[q + h] = lam[n];
+        vm[q + h] = mu[n];
+      }
+    };
+    load(0, 0);
+    for (int k = 0; k < nz; ++k) {
+      load(k + 1, 4);
+      const size_t e = (size_t)k * nx * ny + (size_t)je * nx + ie;
+      const double g[3] = {gu[e], gu[E + e], gu[2 * E + e]};
+      // centre terms
+      double cj[3][3], r[3][3], gl[3], gm[3];
+      centre_jacobian(xe, cj);
+      const double det0 = adjugate(cj[0], cj[1], cj[2], r);
+      centre_ref_grad(vl, gl);
+      centre_ref_grad(vm, gm);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double tl = gl[0] * r[0][d] + gl[1] * r[1][d] + gl[2] * r[2][d];  // det * grad lambda
+        const double tm = gm[0] * r[0][d] + gm[1] * r[1][d] + gm[2] * r[2][d];  // det * grad mu
+        dL_du0[d * E + e] = (float)(g[d] - 8.0 * tm);
+        acc[d] += g[d] * tl / det0;
+      }
+      // Gauss-point terms
+      double Jg[3][3][4], el[3][4], em[3][4], Gl[3][4], Gm[3][4];
+      gauss_jacobian(xe, Jg);
+      edge_diffs(vl, el);
+      edge_diffs(vm, em);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        bil4(el[m], Gl[m]);
+        bil4(em[m], Gm[m]);
+      }
+#pragma unroll
+      for (int gp = 0; gp < 8; ++gp) {
+        GP_PAIRS(gp & 1, (gp >> 1) & 1, gp >> 2);
+        const double c0[3] = {Jg[0][0][p0], Jg[0][1][p0], Jg[0][2][p0]};
+        const double c1[3] = {Jg[1][0][p1], Jg[1][1][p1], Jg[1][2][p1]};
+        const double c2[3] = {Jg[2][0][p2], Jg[2][1][p2], Jg[2][2][p2]};
+        double rr[3][3];
+        const double det = adjugate(c0, c1, c2, rr);
+        const double idet = 1.0 / det;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double tl = 0.5 * (Gl[0][p0] * rr[0][d] + Gl[1][p1] * rr[1][d] + Gl[2][p2] * rr[2][d]);
+          const double tm = 0.5 * (Gm[0][p0] * rr[0][d] + Gm[1][p1] * rr[1][d] + Gm[2][p2] * rr[2][d]);
+          acc[d] -= tl * tm * idet;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xe[d][q] = xe[d][q + 4];
+        vl[q] = vl[q + 4];
+        vm[q] = vm[q + 4];
+      }
+    }
+  }
+  const int t = threadIdx.x;
+  const int nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    s_red[t] = acc[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) s_red[t] += s_red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) partials[(size_t)d * nb + bid] = s_red[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void sumsq_kernel(const double* __restrict__ v, size_t n,
+                                                    double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double a = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    a += v[i] * v[i];
+  s_red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
+}
+
+TileArgs tile_args(const mcw_handle& h) {
+  TileArgs A{};
+  A.X = h.X.as<double>();
+  A.Y = h.Y.as<double>();
+  A.Z = h.Z.as<double>();
+  A.nx = h.d.nx;
+  A.ny = h.d.ny;
+  A.nz = h.d.nz;
+  A.c[0] = h.c[0];
+  A.c[1] = h.c[1];
+  A.c[2] = h.c[2];
+  A.faces = h.faces;
+  return A;
+}
+
+dim3 tile_grid(const mcw_handle& h) {
+  return dim3((h.d.NX() + TN - 1) / TN, (h.d.NY() + TN - 1) / TN);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void launch_geometry_check(const mcw_handle& h, long long* first_bad) {
+  const long long E = (long long)h.d.nx * h.d.ny * h.d.nz;
+  const unsigned blocks = (unsigned)((E + 255) / 256);
+  geometry_check_kernel<<<blocks, 256, 0, h.stream>>>(h.X.as<double>(), h.Y.as<double>(),
+                                                      h.Z.as<double>(), h.d.nx, h.d.ny, h.d.nz,
+                                                      reinterpret_cast<unsigned long long*>(first_bad));
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_assemble_stencil(const mcw_handle& h, double* st64) {
+  const int nx = h.d.nx, ny = h.d.ny, nz = h.d.nz;
+  for (int pk = 0; pk < 2; ++pk)
+    for (int pj = 0; pj < 2; ++pj)
+      for (int pi = 0; pi < 2; ++pi) {
+        const long long m = (long long)((nx - pi + 1) / 2) * ((ny - pj + 1) / 2) * ((nz - pk + 1) / 2);
+        if (m == 0) continue;
+        assemble_kernel<<<(unsigned)((m + 255) / 256), 256, 0, h.stream>>>(
+            h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(), nx, ny, nz, h.c[0], h.c[1],
+            h.c[2], pi, pj, pk, st64);
+        MCW_CHECK_LAUNCH();
+      }
+}
+
+// mode 0: out = K x (no boundary conditions); mode 1: out = f - K x at free nodes, 0 elsewhere.
+void launch_apply(const mcw_handle& h, const double* x, const double* f, double* out, int mode,
+                  double* partials, size_t* n_part) {
+  TileArgs A = tile_args(h);
+  A.v = x;
+  A.f = f;
+  A.out = out;
+  A.partials = partials;
+  const dim3 g = tile_grid(h);
+  if (mode == 0)
+    elem_tile_kernel<M_APPLY><<<g, 256, 0, h.stream>>>(A);
+  else
+    elem_tile_kernel<M_RESID><<<g, 256, 0, h.stream>>>(A);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partials, size_t* n_part) {
+  TileArgs A = tile_args(h);
+  A.ue = u0;
+  A.out = f;
+  A.partials = partials;
+  const dim3 g = tile_grid(h);
+  elem_tile_kernel<M_RHS><<<g, 256, 0, h.stream>>>(A);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
+                       double* partials, size_t* n_part) {
+  TileArgs A = tile_args(h);
+  A.ue = u0;
+  A.v = lam;
+  A.out = D;
+  A.partials = partials;
+  const dim3 g = tile_grid(h);
+  elem_tile_kernel<M_DIV><<<g, 256, 0, h.stream>>>(A);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_lam, double* partials,
+                            size_t* n_part) {
+  TileArgs A = tile_args(h);
+  A.ue = g_u;
+  A.out = g_lam;
+  A.partials = partials;
+  const dim3 g = tile_grid(h);
+  elem_tile_kernel<M_ADJ><<<g, 256, 0, h.stream>>>(A);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u) {
+  const dim3 g((h.d.nx + 63) / 64, (h.d.ny + 3) / 4);
+  recover_kernel<<<g, 256, 0, h.stream>>>(h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(),
+                                          lam, u0, u, h.d.nx, h.d.ny, h.d.nz, h.c[0], h.c[1],
+                                          h.c[2]);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const double* lam,
+                             const double* mu, float* dL_du0, double* partials, size_t* n_part) {
+  const dim3 g((h.d.nx + 63) / 64, (h.d.ny + 3) / 4);
+  adjoint_elem_kernel<<<g, 256, 0, h.stream>>>(h.X.as<double>(), h.Y.as<double>(),
+                                               h.Z.as<double>(), lam, mu, g_u, dL_du0, partials,
+                                               h.d.nx, h.d.ny, h.d.nz);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_check_finite(const mcw_handle& h, const double* v, size_t n, double* partials,
+                         size_t* n_part) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  sumsq_kernel<<<blocks, 256, 0, h.stream>>>(v, n, partials);
+  MCW_CHECK_LAUNCH();
+  if (n_part) *n_part = blocks;
+}
+
+}  // namespace mcw

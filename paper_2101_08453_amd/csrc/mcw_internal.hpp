@@ -1,0 +1,200 @@
+// Internal declarations shared by the libmcwind sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mcwind.h"
+
+namespace mcw {
+
+// ---------------------------------------------------------------- errors
+
+struct Error {
+  mcw_status status;
+  std::string msg;
+};
+
+#define MCW_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::mcw::Error{e_ == hipErrorOutOfMemory ? MCW_OOM : MCW_HIP_ERROR,         \
+                         std::string(#call) + ": " + hipGetErrorString(e_)};          \
+  } while (0)
+
+#define MCW_CHECK_LAUNCH() MCW_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- device buffers
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    MCW_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- grid geometry
+
+// Node-grid dimensions of one level: NX = nx+1 nodes in x, etc.
+struct Dims {
+  int nx, ny, nz;  // elements
+  int NX() const { return nx + 1; }
+  int NY() const { return ny + 1; }
+  int NZ() const { return nz + 1; }
+  size_t N() const { return (size_t)NX() * NY() * NZ(); }
+  // even x indices first in every stencil row: index of i inside its row
+  int NXe() const { return (NX() + 1) >> 1; }
+};
+
+// Free-node test: a node is fixed iff it lies on a face outside Gamma.
+struct Faces {
+  uint32_t gamma;
+  __host__ __device__ bool x_fixed(int i, int NX) const {
+    return (i == 0 && !(gamma & MCW_GAMMA_XLO)) || (i == NX - 1 && !(gamma & MCW_GAMMA_XHI));
+  }
+  __host__ __device__ bool y_fixed(int j, int NY) const {
+    return (j == 0 && !(gamma & MCW_GAMMA_YLO)) || (j == NY - 1 && !(gamma & MCW_GAMMA_YHI));
+  }
+  __host__ __device__ int k_first() const { return (gamma & MCW_GAMMA_BOTTOM) ? 0 : 1; }
+  __host__ __device__ int k_last(int NZ) const { return (gamma & MCW_GAMMA_TOP) ? NZ - 1 : NZ - 2; }
+};
+
+// Interpolation between a level and the next coarser one, per direction.
+// Fine index p maps to coarse lo[p], hi[p] (equal when p is kept, weight 1;
+// else weight 1/2 each).  Coarse index c has fine centre ctr[c] and support
+// [slo[c], shi[c]] (the kept node and its dropped neighbours).
+struct DirMap {
+  int nf = 0, nc = 0;  // node counts
+  std::vector<int> lo, hi, ctr, slo, shi;
+};
+
+struct DirMapDev {
+  const int* lo;
+  const int* hi;
+  const int* ctr;
+  const int* slo;
+  const int* shi;
+};
+
+struct Level {
+  Dims d;
+  std::vector<int> keep_z;  // kept planes towards the next level (empty at the coarsest)
+  int coarsen_h = 0;
+  DevBuf st64;              // 27 x N FP64 stencil, rows split even/odd in x
+  DevBuf st32;              // 27 x N FP32 stencil (FP32_REFINE), same layout
+  DevBuf x, f, r;           // level vectors in V-cycle precision
+  DirMap mx, my, mz;        // to the next coarser level
+  DevBuf maps;              // device copies of the three DirMaps
+  DirMapDev dmx{}, dmy{}, dmz{};
+  double h1 = 0, h2 = 0;
+  std::vector<double> h3;
+};
+
+}  // namespace mcw
+
+struct mcw_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  mcw_options opt{};
+  mcw::Dims d{};
+  mcw::Faces faces{};
+  double a[3]{};
+  double c[3]{};  // a_d^-2
+  mcw::DevBuf X, Y, Z;
+  std::vector<mcw::Level> levels;
+  // coarsest level direct solve: inverse of K_L on its free nodes (FP64)
+  int n_coarse = 0;
+  mcw::DevBuf coarse_inv;   // n_coarse x n_coarse, symmetric
+  mcw::DevBuf coarse_idx;   // n_coarse node numbers of the free coarsest nodes
+  // FP64 outer-loop work vectors (fine level)
+  mcw::DevBuf f64, r64, t64;
+  // reductions
+  mcw::DevBuf partials;     // per-block partial sums (double)
+  mcw::DevBuf scalars;      // device results of reductions
+  size_t n_partials = 0;
+  double* host_scalars = nullptr;  // pinned
+  mcw::DevBuf flag;         // geometry check result
+  hipEvent_t ev[8]{};
+  // hipGraph of one FP32 V-cycle (level vectors are fixed per handle)
+  hipGraphExec_t vgraph = nullptr;
+  bool vgraph_ready = false;
+  std::string last_error;
+};
+
+namespace mcw {
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+
+// Element geometry and element-tile kernels
+void launch_geometry_check(const mcw_handle& h, long long* first_bad);
+void launch_assemble_stencil(const mcw_handle& h, double* st64);
+void launch_apply(const mcw_handle& h, const double* x, const double* f, double* out, int mode,
+                  double* partials, size_t* n_part);
+void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partials, size_t* n_part);
+void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
+                       double* partials, size_t* n_part);
+void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u);
+void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_lam, double* partials,
+                            size_t* n_part);
+void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const double* lam,
+                             const double* mu, float* dL_du0, double* partials, size_t* n_part);
+void launch_check_finite(const mcw_handle& h, const double* v, size_t n, double* partials,
+                         size_t* n_part);
+
+// Multigrid kernels (templated on the V-cycle precision)
+template <class T>
+void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
+                         hipStream_t s);
+template <class T>
+void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
+                     double* partials, size_t* n_part, hipStream_t s);
+template <class T>
+void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
+                     const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s);
+template <class T>
+void launch_prolong_dims(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
+                         const DirMapDev& my, const DirMapDev& mz, const T* e, T* x,
+                         hipStream_t s);
+template <class T>
+void launch_coarse_solve(int n, const double* inv, const int* idx, const T* r, T* e, hipStream_t s);
+template <class T>
+void launch_fill(T* p, size_t n, T v, hipStream_t s);
+
+void launch_rap(const Dims& df, const Dims& dc, const DirMapDev& mx, const DirMapDev& my,
+                const DirMapDev& mz, const double* stf, double* stc, hipStream_t s);
+void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStream_t s);
+void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double, hipStream_t s);
+void launch_scale_to_f32(const Dims& d, const Faces& fc, const double* r, double scale, float* r32,
+                         hipStream_t s);
+void launch_update_lambda(size_t n, const float* e, double inv_scale, double* lam, hipStream_t s);
+void launch_axpy64(size_t n, double alpha, const double* x, double* y, hipStream_t s);
+void launch_zero_fixed(const Dims& d, const Faces& fc, double* v, hipStream_t s);
+void launch_sum_partials(const double* partials, size_t n_part, int width, double* out,
+                         hipStream_t s);
+
+}  // namespace mcw

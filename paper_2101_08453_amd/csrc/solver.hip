@@ -1,0 +1,1017 @@
+// Host side of libmcwind: grid set-up (geometry check, fine stencil, coarse
+// grid hierarchy, Galerkin operators, coarsest factorisation), the solve
+// drivers (plain FP64 multigrid, and FP32 V-cycles inside FP64 iterative
+// refinement), the adjoint, and the extern "C" entry points of mcwind.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+
+#include "mcw_internal.hpp"
+
+using namespace mcw;
+
+namespace {
+
+thread_local std::string g_error;
+
+struct Fail {
+  static void arg(const std::string& m) { throw Error{MCW_INVALID_ARG, m}; }
+};
+
+void logf(const mcw_handle& h, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void logf(const mcw_handle& h, const char* fmt, ...) {
+  if (!h.opt.verbose) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[mcwind] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  va_end(ap);
+}
+
+// ---------------------------------------------------------------- hierarchy rule
+
+// Counts of free nodes of a level.
+size_t free_count(const Dims& d, const Faces& f) {
+  auto cnt = [](int n, bool lo_fixed, bool hi_fixed) {
+    return std::max(0, n - (lo_fixed ? 1 : 0) - (hi_fixed ? 1 : 0));
+  };
+  const size_t fx = cnt(d.NX(), f.x_fixed(0, d.NX()), f.x_fixed(d.NX() - 1, d.NX()));
+  const size_t fy = cnt(d.NY(), f.y_fixed(0, d.NY()), f.y_fixed(d.NY() - 1, d.NY()));
+  const int k0 = f.k_first(), k1 = f.k_last(d.NZ());
+  const size_t fz = k1 >= k0 ? (size_t)(k1 - k0 + 1) : 0;
+  return fx * fy * fz;
+}
+
+std::vector<int> keep_every_other(int n) {
+  std::vector<int> k;
+  for (int p = 0; p <= n; p += 2) k.push_back(p);
+  if (k.back() != n) k.push_back(n);
+  return k;
+}
+
+std::vector<int> keep_all(int n) {
+  std::vector<int> k(n + 1);
+  for (int p = 0; p <= n; ++p) k[p] = p;
+  return k;
+}
+
+DirMap make_map(int n, const std::vector<int>& keep) {
+  DirMap m;
+  m.nf = n + 1;
+  m.nc = (int)keep.size();
+  std::vector<int> idx(n + 1, -1);
+  for (int c = 0; c < m.nc; ++c) idx[keep[c]] = c;
+  m.lo.resize(n + 1);
+  m.hi.resize(n + 1);
+  for (int p = 0; p <= n; ++p) {
+    if (idx[p] >= 0) {
+      m.lo[p] = m.hi[p] = idx[p];
+    } else {
+      m.lo[p] = idx[p - 1];
+      m.hi[p] = idx[p + 1];
+    }
+  }
+  m.ctr = keep;
+  m.slo.resize(m.nc);
+  m.shi.resize(m.nc);
+  for (int c = 0; c < m.nc; ++c) {
+    const int p = keep[c];
+    m.slo[c] = (p - 1 >= 0 && idx[p - 1] < 0) ? p - 1 : p;
+    m.shi[c] = (p + 1 <= n && idx[p + 1] < 0) ? p + 1 : p;
+  }
+  return m;
+}
+
+// Geometry kept on the host for the coarsening decisions: the bottom planes of
+// X and Y and all of Z, addressed through the fine indices a level keeps.
+struct HostGeom {
+  int NX0 = 0, NY0 = 0;
+  std::vector<double> X0, Y0, Z;
+};
+
+struct LevelIdx {
+  std::vector<int> kx, ky, kz;  // level nodes as fine-grid indices
+};
+
+void spacings(const HostGeom& g, const LevelIdx& li, double& h1, double& h2,
+              std::vector<double>& h3) {
+  const int nxl = (int)li.kx.size() - 1, nyl = (int)li.ky.size() - 1, nzl = (int)li.kz.size() - 1;
+  double sx = 0.0, sy = 0.0;
+  for (int j : li.ky) sx += g.X0[(size_t)j * g.NX0 + li.kx.back()] - g.X0[(size_t)j * g.NX0 + li.kx.front()];
+  for (int i : li.kx) sy += g.Y0[(size_t)li.ky.back() * g.NX0 + i] - g.Y0[(size_t)li.ky.front() * g.NX0 + i];
+  h1 = sx / ((double)nxl * li.ky.size());
+  h2 = sy / ((double)nyl * li.kx.size());
+  h3.assign(nzl, 0.0);
+  const size_t plane = (size_t)g.NX0 * g.NY0;
+  for (int k = 0; k < nzl; ++k) {
+    const double* zb = g.Z.data() + (size_t)li.kz[k] * plane;
+    const double* zt = g.Z.data() + (size_t)li.kz[k + 1] * plane;
+    double s = 0.0;
+    for (int j : li.ky) {
+      const size_t row = (size_t)j * g.NX0;
+      for (int i : li.kx) s += zt[row + i] - zb[row + i];
+    }
+    h3[k] = s / ((double)li.kx.size() * li.ky.size());
+  }
+}
+
+// Sec. 3 coarsening decision for one level; false when the level is the coarsest.
+bool decide(const mcw_handle& h, const Dims& d, const Faces& fc, double h1, double h2,
+            const std::vector<double>& h3, bool& ch, std::vector<int>& keep_z) {
+  if ((long long)free_count(d, fc) <= (long long)h.opt.coarse_direct_max) return false;
+  const bool can_h = d.nx >= 3 && d.ny >= 3;
+  const double hh = std::sqrt(h1 * h2);
+  const double ah = std::sqrt(h.a[0] * h.a[1]);
+  auto ratio = [&](double t, double hhor) {
+    return h.opt.coarsen_rule == MCW_COARSEN_LITERAL ? ah * t / (hhor * h.a[2])
+                                                     : h.a[2] * t / (ah * hhor);
+  };
+  keep_z.clear();
+  if (h.opt.coarsen_rule == MCW_COARSEN_FULL) {
+    ch = can_h;
+    keep_z = keep_every_other(d.nz);
+  } else {
+    ch = can_h && ratio(h3[0], hh) > 1.0 / 3.0;
+    const double hh2 = ch ? 2.0 * hh : hh;
+    keep_z.push_back(0);
+    int k = 0;
+    while (k < d.nz) {
+      if (k + 1 < d.nz && ratio(h3[k], hh2) < 3.0) {
+        keep_z.push_back(k + 2);
+        k += 2;
+      } else {
+        keep_z.push_back(k + 1);
+        k += 1;
+      }
+    }
+  }
+  if (!ch && (int)keep_z.size() == d.nz + 1) {
+    if (!can_h) return false;
+    ch = true;
+  }
+  return true;
+}
+
+void upload_maps(Level& L, hipStream_t s) {
+  const DirMap* ms[3] = {&L.mx, &L.my, &L.mz};
+  size_t total = 0;
+  for (auto* m : ms) total += 2 * (size_t)m->nf + 3 * (size_t)m->nc;
+  std::vector<int> host;
+  host.reserve(total);
+  size_t off[3][5];
+  for (int d = 0; d < 3; ++d) {
+    const DirMap& m = *ms[d];
+    off[d][0] = host.size(); host.insert(host.end(), m.lo.begin(), m.lo.end());
+    off[d][1] = host.size(); host.insert(host.end(), m.hi.begin(), m.hi.end());
+    off[d][2] = host.size(); host.insert(host.end(), m.ctr.begin(), m.ctr.end());
+    off[d][3] = host.size(); host.insert(host.end(), m.slo.begin(), m.slo.end());
+    off[d][4] = host.size(); host.insert(host.end(), m.shi.begin(), m.shi.end());
+  }
+  L.maps.alloc(host.size() * sizeof(int));
+  MCW_HIP(hipMemcpyAsync(L.maps.p, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  MCW_HIP(hipStreamSynchronize(s));
+  const int* base = L.maps.as<int>();
+  DirMapDev* dm[3] = {&L.dmx, &L.dmy, &L.dmz};
+  for (int d = 0; d < 3; ++d) {
+    dm[d]->lo = base + off[d][0];
+    dm[d]->hi = base + off[d][1];
+    dm[d]->ctr = base + off[d][2];
+    dm[d]->slo = base + off[d][3];
+    dm[d]->shi = base + off[d][4];
+  }
+}
+
+// ---------------------------------------------------------------- coarsest level
+
+// Dense FP64 inverse of the coarsest operator on its free nodes (Cholesky).
+void factor_coarsest(mcw_handle& h) {
+  Level& L = h.levels.back();
+  const Dims d = L.d;
+  const size_t N = d.N();
+  std::vector<double> st(27 * N);
+  MCW_HIP(hipMemcpyAsync(st.data(), L.st64.p, st.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+  const int NX = d.NX(), NY = d.NY(), NZ = d.NZ(), NXe = d.NXe();
+  std::vector<int> pos(N, -1), idx;
+  const int k0 = h.faces.k_first(), k1 = h.faces.k_last(NZ);
+  for (int k = 0; k < NZ; ++k)
+    for (int j = 0; j < NY; ++j)
+      for (int i = 0; i < NX; ++i) {
+        if (h.faces.x_fixed(i, NX) || h.faces.y_fixed(j, NY) || k < k0 || k > k1) continue;
+        const size_t n = (size_t)i + (size_t)NX * (j + (size_t)NY * k);
+        pos[n] = (int)idx.size();
+        idx.push_back((int)n);
+      }
+  const int n = (int)idx.size();
+  h.n_coarse = n;
+  if (n == 0) throw Error{MCW_SINGULAR, "the coarsest grid has no free nodes"};
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    const size_t nd = (size_t)idx[r];
+    const int i = (int)(nd % NX), j = (int)((nd / NX) % NY), k = (int)(nd / ((size_t)NX * NY));
+    const size_t sp = (size_t)k * NX * NY + (size_t)j * NX + ((i & 1) ? NXe + (i >> 1) : (i >> 1));
+    for (int o = 0; o < 27; ++o) {
+      const int ii = i + o % 3 - 1, jj = j + (o / 3) % 3 - 1, kk = k + o / 9 - 1;
+      if (ii < 0 || ii >= NX || jj < 0 || jj >= NY || kk < 0 || kk >= NZ) continue;
+      const int q = pos[(size_t)ii + (size_t)NX * (jj + (size_t)NY * kk)];
+      if (q < 0) continue;
+      A[(size_t)r * n + q] += st[(size_t)o * N + sp];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int q = r + 1; q < n; ++q) {
+      const double s = 0.5 * (A[(size_t)r * n + q] + A[(size_t)q * n + r]);
+      A[(size_t)r * n + q] = A[(size_t)q * n + r] = s;
+    }
+  // Cholesky A = L L^T, L stored in the lower triangle (row major)
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    const double* lj = &A[(size_t)j * n];
+    for (int k = 0; k < j; ++k) s -= lj[k] * lj[k];
+    if (!(s > 0.0)) throw Error{MCW_SINGULAR, "coarsest operator is not positive definite"};
+    const double djj = std::sqrt(s);
+    A[(size_t)j * n + j] = djj;
+    for (int i = j + 1; i < n; ++i) {
+      double* li = &A[(size_t)i * n];
+      double t = li[j];
+      for (int k = 0; k < j; ++k) t -= li[k] * lj[k];
+      li[j] = t / djj;
+    }
+  }
+  // W = L^{-1} (lower), stored transposed: Wt[c][r] = W[r][c] for r >= c
+  std::vector<double> Wt((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    double* w = &Wt[(size_t)c * n];  // column c of W
+    w[c] = 1.0 / A[(size_t)c * n + c];
+    for (int r = c + 1; r < n; ++r) {
+      const double* lr = &A[(size_t)r * n];
+      double t = 0.0;
+      for (int k = c; k < r; ++k) t -= lr[k] * w[k];
+      w[r] = t / lr[r];
+    }
+  }
+  // inverse = W^T W: inv[a][b] = sum_{r >= max(a,b)} W[r][a] W[r][b]
+  std::vector<double> inv((size_t)n * n);
+  for (int a = 0; a < n; ++a) {
+    const double* wa = &Wt[(size_t)a * n];
+    for (int b = a; b < n; ++b) {
+      const double* wb = &Wt[(size_t)b * n];
+      double t = 0.0;
+      for (int r = b; r < n; ++r) t += wa[r] * wb[r];
+      inv[(size_t)a * n + b] = inv[(size_t)b * n + a] = t;
+    }
+  }
+  h.coarse_inv.alloc(inv.size() * sizeof(double));
+  h.coarse_idx.alloc(idx.size() * sizeof(int));
+  MCW_HIP(hipMemcpyAsync(h.coarse_inv.p, inv.data(), inv.size() * sizeof(double),
+                         hipMemcpyHostToDevice, h.stream));
+  MCW_HIP(hipMemcpyAsync(h.coarse_idx.p, idx.data(), idx.size() * sizeof(int),
+                         hipMemcpyHostToDevice, h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sum `width` channels of per-block partials into h.scalars and return them on the host.
+void reduce_to_host(mcw_handle& h, size_t n_part, int width, double* out) {
+  launch_sum_partials(h.partials.as<double>(), n_part, width, h.scalars.as<double>(), h.stream);
+  MCW_HIP(hipMemcpyAsync(h.host_scalars, h.scalars.p, width * sizeof(double), hipMemcpyDeviceToHost,
+                         h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+  for (int w = 0; w < width; ++w) out[w] = h.host_scalars[w];
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+template <class T> const T* stencil_of(const Level& L);
+template <> const double* stencil_of<double>(const Level& L) { return L.st64.as<double>(); }
+template <> const float* stencil_of<float>(const Level& L) { return L.st32.as<float>(); }
+
+template <class T>
+void vcycle(mcw_handle& h, int l, T* x, const T* f) {
+  Level& L = h.levels[l];
+  if (l == (int)h.levels.size() - 1) {
+    launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(), f, x,
+                           h.stream);
+    return;
+  }
+  const T* st = stencil_of<T>(L);
+  for (int s = 0; s < h.opt.nu_pre; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream);
+  launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream);
+  Level& C = h.levels[l + 1];
+  launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
+  launch_fill<T>(C.x.as<T>(), C.d.N(), T(0), h.stream);
+  vcycle<T>(h, l + 1, C.x.as<T>(), C.f.as<T>());
+  launch_prolong_dims<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, C.x.as<T>(), x, h.stream);
+  for (int s = 0; s < h.opt.nu_post; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream);
+}
+
+// One FP32 V-cycle on the level-0 buffers, replayed from a hipGraph when enabled.
+void vcycle_f32(mcw_handle& h) {
+  Level& L0 = h.levels[0];
+  if (h.opt.use_graph) {
+    if (!h.vgraph_ready) {
+      hipGraph_t g = nullptr;
+      MCW_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
+      try {
+        vcycle<float>(h, 0, L0.x.as<float>(), L0.f.as<float>());
+      } catch (...) {
+        (void)hipStreamEndCapture(h.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      MCW_HIP(hipStreamEndCapture(h.stream, &g));
+      const hipError_t e = hipGraphInstantiate(&h.vgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      MCW_HIP(e);
+      h.vgraph_ready = true;
+    }
+    MCW_HIP(hipGraphLaunch(h.vgraph, h.stream));
+  } else {
+    vcycle<float>(h, 0, L0.x.as<float>(), L0.f.as<float>());
+  }
+}
+
+// ---------------------------------------------------------------- solve drivers
+
+struct Progress {
+  int outer = 0, cycles = 0;
+  double rel = 0.0;
+  std::vector<double> hist;
+  float ms_outer = 0.f;
+};
+
+// Solve K lam = h.f64 (free nodes) from the starting lam; fnorm = ||f||.
+mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
+  Level& L0 = h.levels[0];
+  const size_t N = h.d.N();
+  const double tol = h.opt.rtol;
+  size_t np = 0;
+  double rr = 0.0;
+  if (h.opt.precision == MCW_FP64) {
+    for (;;) {
+      launch_residual<double>(L0.d, h.faces, L0.st64.as<double>(), lam, h.f64.as<double>(),
+                              h.r64.as<double>(), h.partials.as<double>(), &np, h.stream);
+      reduce_to_host(h, np, 1, &rr);
+      pg.rel = std::sqrt(rr) / fnorm;
+      pg.hist.push_back(pg.rel);
+      ++pg.outer;
+      logf(h, "fp64 cycle %d  rel residual %.3e", pg.cycles, pg.rel);
+      if (!std::isfinite(pg.rel)) return MCW_NONFINITE;
+      if (pg.rel <= tol) return MCW_OK;
+      if (pg.cycles >= h.opt.max_cycles) return MCW_NOT_CONVERGED;
+      vcycle<double>(h, 0, lam, h.f64.as<double>());
+      ++pg.cycles;
+    }
+  }
+  // FP32 V-cycles inside FP64 iterative refinement
+  double rho_est = 0.3, prev_rel = -1.0;
+  int prev_m = 0, stall = 0;
+  const double nfree = (double)std::max<size_t>(free_count(h.d, h.faces), 1);
+  for (;;) {
+    MCW_HIP(hipEventRecord(h.ev[4], h.stream));
+    launch_apply(h, lam, h.f64.as<double>(), h.r64.as<double>(), 1, h.partials.as<double>(), &np);
+    MCW_HIP(hipEventRecord(h.ev[5], h.stream));
+    reduce_to_host(h, np, 1, &rr);
+    float ms = 0.f;
+    MCW_HIP(hipEventElapsedTime(&ms, h.ev[4], h.ev[5]));
+    pg.ms_outer += ms;
+    pg.rel = std::sqrt(rr) / fnorm;
+    pg.hist.push_back(pg.rel);
+    ++pg.outer;
+    logf(h, "refine step %d after %d cycles  rel residual %.3e", pg.outer, pg.cycles, pg.rel);
+    if (!std::isfinite(pg.rel)) return MCW_NONFINITE;
+    if (pg.rel <= tol) return MCW_OK;
+    if (pg.cycles >= h.opt.max_cycles) return MCW_NOT_CONVERGED;
+    if (prev_rel > 0.0 && prev_m > 0) {
+      const double red = pg.rel / prev_rel;
+      if (red > 0.95) {
+        if (++stall >= 3) return MCW_NOT_CONVERGED;
+      } else {
+        stall = 0;
+      }
+      rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / prev_m)));
+    }
+    int m = h.opt.inner_cycles;
+    if (m <= 0) {
+      // reduce to the tolerance in one step, but not below what FP32 can resolve
+      const double target = std::max(tol / pg.rel, 3e-5);
+      m = (int)std::ceil(std::log(target) / std::log(rho_est));
+      m = std::max(1, std::min(m, 12));
+    }
+    m = std::min(m, h.opt.max_cycles - pg.cycles);
+    const double rms = std::sqrt(rr / nfree);
+    const double scale = std::ldexp(1.0, -std::ilogb(rms));
+    launch_scale_to_f32(h.d, h.faces, h.r64.as<double>(), scale, L0.f.as<float>(), h.stream);
+    launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
+    for (int c = 0; c < m; ++c) vcycle_f32(h);
+    launch_update_lambda(N, L0.x.as<float>(), 1.0 / scale, lam, h.stream);
+    pg.cycles += m;
+    prev_m = m;
+    prev_rel = pg.rel;
+  }
+}
+
+void fill_info(const mcw_handle& h, const Progress& pg, mcw_info* info) {
+  if (!info) return;
+  info->outer_steps = pg.outer;
+  info->cycles = pg.cycles;
+  info->rel_residual = pg.rel;
+  info->n_levels = (int)h.levels.size();
+  for (int l = 0; l < info->n_levels && l < MCW_MAX_LEVELS; ++l) {
+    info->level_dims[l][0] = h.levels[l].d.nx;
+    info->level_dims[l][1] = h.levels[l].d.ny;
+    info->level_dims[l][2] = h.levels[l].d.nz;
+  }
+  info->n_history = (int)std::min<size_t>(pg.hist.size(), MCW_HISTORY);
+  for (int i = 0; i < info->n_history; ++i) info->history[i] = pg.hist[i];
+  info->rho = 0.0;
+  if (pg.cycles > 0 && !pg.hist.empty() && pg.hist.front() > 0.0 && pg.hist.back() > 0.0)
+    info->rho = std::pow(pg.hist.back() / pg.hist.front(), 1.0 / pg.cycles);
+  info->ms_outer = pg.ms_outer;
+}
+
+mcw_status solve_impl(mcw_handle& h, const double* u0, double* lam, double* u, mcw_info* info) {
+  if (!u0 || !lam) Fail::arg("u0 and lambda must be non-null");
+  if (info) std::memset(info, 0, sizeof(*info));
+  const size_t N = h.d.N();
+  const size_t E = (size_t)h.d.nx * h.d.ny * h.d.nz;
+  MCW_HIP(hipEventRecord(h.ev[0], h.stream));
+  launch_zero_fixed(h.d, h.faces, lam, h.stream);
+  size_t np = 0;
+  double ff = 0.0;
+  launch_rhs(h, u0, h.f64.as<double>(), h.partials.as<double>(), &np);
+  MCW_HIP(hipEventRecord(h.ev[1], h.stream));
+  reduce_to_host(h, np, 1, &ff);
+  const double fnorm = std::sqrt(ff);
+  Progress pg;
+  mcw_status st = MCW_OK;
+  if (!std::isfinite(fnorm)) {
+    st = MCW_NONFINITE;
+    h.last_error = "non-finite right-hand side (check u0)";
+  } else if (fnorm == 0.0) {
+    launch_fill<double>(lam, N, 0.0, h.stream);
+  } else {
+    st = iterate(h, lam, fnorm, pg);
+    if (st == MCW_NOT_CONVERGED)
+      h.last_error = "not converged: relative residual " + std::to_string(pg.rel);
+    if (st == MCW_NONFINITE) h.last_error = "non-finite residual";
+  }
+  MCW_HIP(hipEventRecord(h.ev[2], h.stream));
+  double div[2] = {0.0, 0.0};
+  if (st == MCW_OK || st == MCW_NOT_CONVERGED) {
+    if (u) launch_recover(h, u0, lam, u);
+    launch_divergence(h, u0, lam, h.t64.as<double>(), h.partials.as<double>(), &np);
+    reduce_to_host(h, np, 2, div);
+  } else if (u) {
+    MCW_HIP(hipMemcpyAsync(u, u0, 3 * E * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+  }
+  MCW_HIP(hipEventRecord(h.ev[3], h.stream));
+  MCW_HIP(hipEventSynchronize(h.ev[3]));
+  if (info) {
+    fill_info(h, pg, info);
+    info->f_norm = fnorm;
+    info->rel_divergence = div[1] > 0.0 ? std::sqrt(div[0] / div[1]) : std::sqrt(div[0]);
+    float t = 0.f;
+    MCW_HIP(hipEventElapsedTime(&t, h.ev[0], h.ev[3])); info->ms_total = t;
+    MCW_HIP(hipEventElapsedTime(&t, h.ev[0], h.ev[1])); info->ms_rhs = t;
+    MCW_HIP(hipEventElapsedTime(&t, h.ev[1], h.ev[2])); info->ms_cycles = t - pg.ms_outer;
+    MCW_HIP(hipEventElapsedTime(&t, h.ev[2], h.ev[3])); info->ms_finish = t;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------- set-up
+
+void validate(const mcw_grid_desc* g, const mcw_options& o) {
+  if (!g) Fail::arg("grid descriptor is null");
+  if (!g->X || !g->Y || !g->Z) Fail::arg("node coordinate arrays must be non-null");
+  if (g->nx < 2 || g->ny < 2 || g->nz < 1) Fail::arg("need nx >= 2, ny >= 2, nz >= 1");
+  if ((long long)(g->nx + 1) * (g->ny + 1) > (1LL << 30) || g->nz > 4096)
+    Fail::arg("grid too large");
+  for (int d = 0; d < 3; ++d)
+    if (!(g->a[d] > 0.0) || !std::isfinite(g->a[d])) Fail::arg("penalty constants must be finite and > 0");
+  if (g->gamma_faces > 63u) Fail::arg("gamma_faces has bits beyond the six faces");
+  if (o.precision != MCW_FP64 && o.precision != MCW_FP32_REFINE) Fail::arg("bad precision");
+  if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) Fail::arg("rtol must be in (0, 1)");
+  if (o.max_cycles < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post < 1)
+    Fail::arg("bad cycle or smoothing counts");
+  if (o.coarsen_rule < 0 || o.coarsen_rule > 2) Fail::arg("bad coarsening rule");
+  if (o.coarse_direct_max < 1 || o.coarse_direct_max > 4096) Fail::arg("coarse_direct_max must be in [1, 4096]");
+}
+
+void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, mcw_handle& h) {
+  validate(g, opt);
+  if (g->gamma_faces == 63u)
+    throw Error{MCW_SINGULAR, "Gamma covers every face: lambda is only defined up to a constant"};
+  h.opt = opt;
+  MCW_HIP(hipGetDevice(&h.device));
+  h.stream = static_cast<hipStream_t>(stream);
+  if (!h.stream) {
+    // a stream of our own (graph capture needs one); it synchronises with the default stream
+    MCW_HIP(hipStreamCreate(&h.stream));
+    h.own_stream = true;
+  }
+  h.d = Dims{g->nx, g->ny, g->nz};
+  h.faces = Faces{g->gamma_faces};
+  for (int d = 0; d < 3; ++d) {
+    h.a[d] = g->a[d];
+    h.c[d] = 1.0 / (g->a[d] * g->a[d]);
+  }
+  for (auto& e : h.ev) MCW_HIP(hipEventCreate(&e));
+  const size_t N = h.d.N();
+  h.X.alloc(N * sizeof(double));
+  h.Y.alloc(N * sizeof(double));
+  h.Z.alloc(N * sizeof(double));
+  MCW_HIP(hipMemcpyAsync(h.X.p, g->X, N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+  MCW_HIP(hipMemcpyAsync(h.Y.p, g->Y, N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+  MCW_HIP(hipMemcpyAsync(h.Z.p, g->Z, N * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+
+  // a1: geometry
+  h.flag.alloc(sizeof(unsigned long long));
+  const unsigned long long none = ~0ULL;
+  MCW_HIP(hipMemcpyAsync(h.flag.p, &none, sizeof(none), hipMemcpyHostToDevice, h.stream));
+  launch_geometry_check(h, h.flag.as<long long>());
+  unsigned long long bad = 0;
+  MCW_HIP(hipMemcpyAsync(&bad, h.flag.p, sizeof(bad), hipMemcpyDeviceToHost, h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+  if (bad != none) {
+    const unsigned long long nx = g->nx, ny = g->ny;
+    throw Error{MCW_BAD_GEOMETRY, "det J <= 0 in element (" + std::to_string(bad % nx) + ", " +
+                                      std::to_string((bad / nx) % ny) + ", " +
+                                      std::to_string(bad / (nx * ny)) + ")"};
+  }
+
+  // host geometry for the coarsening decisions
+  HostGeom hg;
+  hg.NX0 = h.d.NX();
+  hg.NY0 = h.d.NY();
+  const size_t plane = (size_t)hg.NX0 * hg.NY0;
+  hg.X0.resize(plane);
+  hg.Y0.resize(plane);
+  hg.Z.resize(N);
+  MCW_HIP(hipMemcpyAsync(hg.X0.data(), h.X.p, plane * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  MCW_HIP(hipMemcpyAsync(hg.Y0.data(), h.Y.p, plane * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  MCW_HIP(hipMemcpyAsync(hg.Z.data(), h.Z.p, N * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+
+  // a3: the hierarchy of logically Cartesian coarse grids
+  LevelIdx li{keep_all(h.d.nx), keep_all(h.d.ny), keep_all(h.d.nz)};
+  h.levels.clear();
+  h.levels.emplace_back();
+  h.levels[0].d = h.d;
+  for (;;) {
+    Level& L = h.levels.back();
+    spacings(hg, li, L.h1, L.h2, L.h3);
+    bool ch = false;
+    std::vector<int> kz;
+    if ((int)h.levels.size() >= MCW_MAX_LEVELS || !decide(h, L.d, h.faces, L.h1, L.h2, L.h3, ch, kz))
+      break;
+    L.coarsen_h = ch ? 1 : 0;
+    L.keep_z = kz;
+    const std::vector<int> kx = ch ? keep_every_other(L.d.nx) : keep_all(L.d.nx);
+    const std::vector<int> ky = ch ? keep_every_other(L.d.ny) : keep_all(L.d.ny);
+    L.mx = make_map(L.d.nx, kx);
+    L.my = make_map(L.d.ny, ky);
+    L.mz = make_map(L.d.nz, kz);
+    LevelIdx nl;
+    for (int p : kx) nl.kx.push_back(li.kx[p]);
+    for (int p : ky) nl.ky.push_back(li.ky[p]);
+    for (int p : kz) nl.kz.push_back(li.kz[p]);
+    li = nl;
+    Level C;
+    C.d = Dims{(int)kx.size() - 1, (int)ky.size() - 1, (int)kz.size() - 1};
+    h.levels.push_back(std::move(C));
+  }
+  hg = HostGeom();
+  for (size_t l = 0; l + 1 < h.levels.size(); ++l) upload_maps(h.levels[l], h.stream);
+
+  // a2 + a4: fine stencil by 2x2x2 Gauss, Galerkin coarse operators in FP64
+  const bool f32 = opt.precision == MCW_FP32_REFINE;
+  Level& L0 = h.levels[0];
+  L0.st64.alloc(27 * N * sizeof(double));
+  launch_fill<double>(L0.st64.as<double>(), 27 * N, 0.0, h.stream);
+  launch_assemble_stencil(h, L0.st64.as<double>());
+  for (size_t l = 0; l < h.levels.size(); ++l) {
+    Level& L = h.levels[l];
+    if (l + 1 < h.levels.size()) {
+      Level& C = h.levels[l + 1];
+      C.st64.alloc(27 * C.d.N() * sizeof(double));
+      launch_rap(L.d, C.d, L.dmx, L.dmy, L.dmz, L.st64.as<double>(), C.st64.as<double>(), h.stream);
+    }
+    if (f32) {
+      L.st32.alloc(27 * L.d.N() * sizeof(float));
+      launch_round_stencil(L.d, L.st64.as<double>(), L.st32.as<float>(), h.stream);
+      if (l + 1 < h.levels.size()) {
+        MCW_HIP(hipStreamSynchronize(h.stream));
+        L.st64.release();
+      }
+    }
+  }
+  // a5: coarsest direct solve
+  factor_coarsest(h);
+  if (f32) h.levels.back().st64.release();
+
+  // level vectors
+  for (size_t l = 0; l < h.levels.size(); ++l) {
+    Level& L = h.levels[l];
+    const size_t n = L.d.N();
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    if (l > 0 || f32) {
+      L.x.alloc(n * es);
+      L.f.alloc(n * es);
+    }
+    if (l + 1 < h.levels.size()) L.r.alloc(n * es);
+    if (L.x.p) {
+      if (f32) launch_fill<float>(L.x.as<float>(), n, 0.f, h.stream);
+      else launch_fill<double>(L.x.as<double>(), n, 0.0, h.stream);
+    }
+  }
+  h.f64.alloc(N * sizeof(double));
+  h.r64.alloc(N * sizeof(double));
+  h.t64.alloc(N * sizeof(double));
+  // per-block partial sums: the largest user is the element-tile grid (2 channels)
+  const size_t tiles = (size_t)((h.d.NX() + 14) / 15) * ((h.d.NY() + 14) / 15);
+  const size_t cols = (size_t)((h.d.NX() + 63) / 64) * ((h.d.NY() + 3) / 4);
+  const size_t ecols = (size_t)((h.d.nx + 63) / 64) * ((h.d.ny + 3) / 4);
+  h.n_partials = std::max({2 * tiles, cols, 3 * ecols, (size_t)4096});
+  h.partials.alloc(h.n_partials * sizeof(double));
+  h.scalars.alloc(8 * sizeof(double));
+  MCW_HIP(hipHostMalloc((void**)&h.host_scalars, 8 * sizeof(double), hipHostMallocDefault));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+  if (opt.verbose) {
+    for (size_t l = 0; l < h.levels.size(); ++l) {
+      const Level& L = h.levels[l];
+      logf(h, "level %zu: %d x %d x %d elements, h1 %.3g, h3[0] %.3g, coarsen_h %d, planes kept %zu", l,
+           L.d.nx, L.d.ny, L.d.nz, L.h1, L.h3.empty() ? 0.0 : L.h3[0], L.coarsen_h, L.keep_z.size());
+    }
+    logf(h, "coarsest free unknowns %d", h.n_coarse);
+  }
+}
+
+void destroy_impl(mcw_handle* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  if (h->vgraph) (void)hipGraphExecDestroy(h->vgraph);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->host_scalars) (void)hipHostFree(h->host_scalars);
+  const bool own = h->own_stream;
+  hipStream_t s = h->stream;
+  delete h;
+  if (own && s) (void)hipStreamDestroy(s);
+}
+
+template <class F>
+mcw_status guarded(mcw_handle* h, F&& fn) {
+  try {
+    return fn();
+  } catch (const Error& e) {
+    if (h) h->last_error = e.msg;
+    g_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (h) h->last_error = "host allocation failed";
+    g_error = "host allocation failed";
+    return MCW_OOM;
+  } catch (...) {
+    if (h) h->last_error = "unexpected exception";
+    g_error = "unexpected exception";
+    return MCW_HIP_ERROR;
+  }
+}
+
+Level& level_at(mcw_handle* h, int l, bool need_coarser) {
+  if (l < 0 || l >= (int)h->levels.size() || (need_coarser && l + 1 >= (int)h->levels.size()))
+    Fail::arg("level index out of range");
+  return h->levels[l];
+}
+
+bool is_f32(const mcw_handle* h) { return h->opt.precision == MCW_FP32_REFINE; }
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+void mcw_default_options(mcw_options* o) {
+  if (!o) return;
+  o->precision = MCW_FP32_REFINE;
+  o->rtol = 1e-8;
+  o->max_cycles = 200;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->inner_cycles = 0;
+  o->coarsen_rule = MCW_COARSEN_OPERATOR;
+  o->coarse_direct_max = 1024;
+  o->use_graph = 1;
+  o->verbose = std::getenv("MCW_LOG") ? 1 : 0;
+}
+
+mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
+                      mcw_handle** out) {
+  if (!out) {
+    g_error = "out must be non-null";
+    return MCW_INVALID_ARG;
+  }
+  *out = nullptr;
+  mcw_options o;
+  if (opts) o = *opts;
+  else mcw_default_options(&o);
+  auto* h = new (std::nothrow) mcw_handle();
+  if (!h) return MCW_OOM;
+  const mcw_status st = guarded(nullptr, [&] {
+    create_impl(g, o, stream, *h);
+    return MCW_OK;
+  });
+  if (st != MCW_OK) {
+    destroy_impl(h);
+    return st;
+  }
+  *out = h;
+  return MCW_OK;
+}
+
+void mcw_destroy(mcw_handle* h) { destroy_impl(h); }
+
+mcw_status mcw_set_tolerance(mcw_handle* h, double rtol, int32_t max_cycles) {
+  if (!h) return MCW_INVALID_ARG;
+  if (!(rtol > 0.0) || !(rtol < 1.0) || max_cycles < 1) {
+    h->last_error = "rtol must be in (0, 1) and max_cycles >= 1";
+    return MCW_INVALID_ARG;
+  }
+  h->opt.rtol = rtol;
+  h->opt.max_cycles = max_cycles;
+  return MCW_OK;
+}
+
+mcw_status mcw_solve(mcw_handle* h, const double* u0, double* lambda, double* u, mcw_info* info) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] { return solve_impl(*h, u0, lambda, u, info); });
+}
+
+mcw_status mcw_solve_batch(int32_t m, mcw_handle* const* hs, const double* const* u0,
+                           double* const* lambda, double* const* u, mcw_info* infos) {
+  if (m < 0 || (m > 0 && (!hs || !u0 || !lambda))) {
+    g_error = "bad batch arguments";
+    return MCW_INVALID_ARG;
+  }
+  mcw_status first = MCW_OK;
+  for (int i = 0; i < m; ++i) {
+    const mcw_status s = mcw_solve(hs[i], u0[i], lambda[i], u ? u[i] : nullptr,
+                                   infos ? &infos[i] : nullptr);
+    if (s != MCW_OK && first == MCW_OK) first = s;
+  }
+  return first;
+}
+
+mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, float* dL_du0,
+                       double dL_da[3], mcw_info* info) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!lambda || !g_u || !dL_du0 || !dL_da) Fail::arg("adjoint arguments must be non-null");
+    if (info) std::memset(info, 0, sizeof(*info));
+    const size_t N = h->d.N();
+    size_t np = 0;
+    double gg = 0.0;
+    // g_lambda = G_1^T diag(c) g_u on the free nodes (right-hand side of the transpose solve)
+    launch_adjoint_scatter(*h, g_u, h->f64.as<double>(), h->partials.as<double>(), &np);
+    reduce_to_host(*h, np, 1, &gg);
+    const double gnorm = std::sqrt(gg);
+    if (!std::isfinite(gnorm)) {
+      h->last_error = "non-finite adjoint right-hand side";
+      return MCW_NONFINITE;
+    }
+    double* mu = h->t64.as<double>();
+    launch_fill<double>(mu, N, 0.0, h->stream);
+    Progress pg;
+    mcw_status st = MCW_OK;
+    if (gnorm > 0.0) st = iterate(*h, mu, gnorm, pg);
+    if (st != MCW_OK && st != MCW_NOT_CONVERGED) return st;
+    double dc[3] = {0.0, 0.0, 0.0};
+    launch_adjoint_elements(*h, g_u, lambda, mu, dL_du0, h->partials.as<double>(), &np);
+    reduce_to_host(*h, np, 3, dc);
+    for (int d = 0; d < 3; ++d) dL_da[d] = -2.0 * dc[d] / (h->a[d] * h->a[d] * h->a[d]);
+    if (info) {
+      fill_info(*h, pg, info);
+      info->f_norm = gnorm;
+    }
+    return st;
+  });
+}
+
+mcw_status mcw_apply_K(mcw_handle* h, const double* x, double* y) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!x || !y) Fail::arg("null vector");
+    launch_apply(*h, x, nullptr, y, 0, nullptr, nullptr);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_rhs(mcw_handle* h, const double* u0, double* f) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!u0 || !f) Fail::arg("null vector");
+    launch_rhs(*h, u0, f, nullptr, nullptr);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_recover(mcw_handle* h, const double* u0, const double* lambda, double* u) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!u0 || !lambda || !u) Fail::arg("null vector");
+    launch_recover(*h, u0, lambda, u);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda, double* D,
+                          double* rel) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!u0 || !lambda || !D) Fail::arg("null vector");
+    size_t np = 0;
+    double s[2];
+    launch_divergence(*h, u0, lambda, D, h->partials.as<double>(), &np);
+    reduce_to_host(*h, np, 2, s);
+    if (rel) *rel = s[1] > 0.0 ? std::sqrt(s[0] / s[1]) : std::sqrt(s[0]);
+    return MCW_OK;
+  });
+}
+
+int32_t mcw_num_levels(const mcw_handle* h) { return h ? (int32_t)h->levels.size() : 0; }
+
+mcw_status mcw_level_info(const mcw_handle* hc, int32_t l, int32_t dims[3], int32_t* coarsen_h,
+                          int32_t* keep_z, int32_t* n_keep) {
+  auto* h = const_cast<mcw_handle*>(hc);
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    const Level& L = level_at(h, l, false);
+    if (dims) {
+      dims[0] = L.d.nx;
+      dims[1] = L.d.ny;
+      dims[2] = L.d.nz;
+    }
+    if (coarsen_h) *coarsen_h = L.coarsen_h;
+    if (n_keep) *n_keep = (int32_t)L.keep_z.size();
+    if (keep_z)
+      for (size_t q = 0; q < L.keep_z.size(); ++q) keep_z[q] = L.keep_z[q];
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!out) Fail::arg("null output");
+    Level& L = level_at(h, l, false);
+    if (prec == MCW_FP64) {
+      if (L.st64.p) {
+        launch_unsplit_stencil(L.d, L.st64.p, out, 1, h->stream);
+      } else if (l == 0) {
+        DevBuf tmp;
+        tmp.alloc(27 * L.d.N() * sizeof(double));
+        launch_fill<double>(tmp.as<double>(), 27 * L.d.N(), 0.0, h->stream);
+        launch_assemble_stencil(*h, tmp.as<double>());
+        launch_unsplit_stencil(L.d, tmp.p, out, 1, h->stream);
+        MCW_HIP(hipStreamSynchronize(h->stream));
+      } else {
+        Fail::arg("FP64 coarse stencils are kept only by FP64 handles");
+      }
+    } else if (prec == MCW_FP32_REFINE) {
+      if (!L.st32.p) Fail::arg("FP32 stencils exist only in FP32_REFINE handles");
+      launch_unsplit_stencil(L.d, L.st32.p, out, 0, h->stream);
+    } else {
+      Fail::arg("bad precision");
+    }
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t sweeps) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!x || !f || sweeps < 0) Fail::arg("bad smoother arguments");
+    Level& L = level_at(h, l, false);
+    for (int s = 0; s < sweeps; ++s) {
+      if (is_f32(h))
+        launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), static_cast<const float*>(f),
+                                   static_cast<float*>(x), h->stream);
+      else
+        launch_smooth_sweep<double>(L.d, h->faces, L.st64.as<double>(), static_cast<const double*>(f),
+                                    static_cast<double*>(x), h->stream);
+    }
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_residual(mcw_handle* h, int32_t l, const void* x, const void* f, void* r) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!x || !f || !r) Fail::arg("null vector");
+    Level& L = level_at(h, l, false);
+    if (is_f32(h))
+      launch_residual<float>(L.d, h->faces, L.st32.as<float>(), static_cast<const float*>(x),
+                             static_cast<const float*>(f), static_cast<float*>(r), nullptr, nullptr,
+                             h->stream);
+    else
+      launch_residual<double>(L.d, h->faces, L.st64.as<double>(), static_cast<const double*>(x),
+                              static_cast<const double*>(f), static_cast<double*>(r), nullptr,
+                              nullptr, h->stream);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_restrict(mcw_handle* h, int32_t l, const void* r, void* rc) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!r || !rc) Fail::arg("null vector");
+    Level& L = level_at(h, l, true);
+    const Level& C = h->levels[l + 1];
+    if (is_f32(h))
+      launch_restrict<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, static_cast<const float*>(r),
+                             static_cast<float*>(rc), h->stream);
+    else
+      launch_restrict<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
+                              static_cast<const double*>(r), static_cast<double*>(rc), h->stream);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_prolong(mcw_handle* h, int32_t l, const void* e, void* x) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!e || !x) Fail::arg("null vector");
+    Level& L = level_at(h, l, true);
+    const Level& C = h->levels[l + 1];
+    if (is_f32(h))
+      launch_prolong_dims<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
+                                 static_cast<const float*>(e), static_cast<float*>(x), h->stream);
+    else
+      launch_prolong_dims<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
+                                  static_cast<const double*>(e), static_cast<double*>(x), h->stream);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!r || !e) Fail::arg("null vector");
+    if (is_f32(h))
+      launch_coarse_solve<float>(h->n_coarse, h->coarse_inv.as<double>(), h->coarse_idx.as<int>(),
+                                 static_cast<const float*>(r), static_cast<float*>(e), h->stream);
+    else
+      launch_coarse_solve<double>(h->n_coarse, h->coarse_inv.as<double>(), h->coarse_idx.as<int>(),
+                                  static_cast<const double*>(r), static_cast<double*>(e), h->stream);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!x || !f) Fail::arg("null vector");
+    if (is_f32(h))
+      vcycle<float>(*h, 0, static_cast<float*>(x), static_cast<const float*>(f));
+    else
+      vcycle<double>(*h, 0, static_cast<double*>(x), static_cast<const double*>(f));
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+const char* mcw_status_string(mcw_status s) {
+  switch (s) {
+    case MCW_OK: return "MCW_OK";
+    case MCW_INVALID_ARG: return "MCW_INVALID_ARG";
+    case MCW_BAD_GEOMETRY: return "MCW_BAD_GEOMETRY";
+    case MCW_SINGULAR: return "MCW_SINGULAR";
+    case MCW_NONFINITE: return "MCW_NONFINITE";
+    case MCW_NOT_CONVERGED: return "MCW_NOT_CONVERGED";
+    case MCW_OOM: return "MCW_OOM";
+    case MCW_HIP_ERROR: return "MCW_HIP_ERROR";
+  }
+  return "unknown status";
+}
+
+const char* mcw_last_error(const mcw_handle* h) { return h ? h->last_error.c_str() : g_error.c_str(); }
+
+}  // extern "C"
