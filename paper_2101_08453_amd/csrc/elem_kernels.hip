@@ -15,6 +15,8 @@
 // gradient g = grad_xi v, the physical gradient is (sum_m g_m r_m) / det J.
 //
 // Local node a = ax + 2 ay + 4 az sits at reference corner (2ax-1, 2ay-1, 2az-1).
+#include <algorithm>
+
 #include "mcw_internal.hpp"
 
 namespace mcw {
@@ -230,9 +232,6 @@ __global__ __launch_bounds__(256) void geometry_check_kernel(const double* __res
 
 // ---------------------------------------------------------------- stencil assembly
 
-// Row-split position of x index i: even indices first, then odd.
-__device__ __forceinline__ int rowpos(int i, int NXe) { return (i & 1) ? NXe + (i >> 1) : (i >> 1); }
-
 // One colour class of elements (parity of i, j, k): elements of a class share
 // no node, so each adds its 8x8 matrix into the node stencils without races.
 __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict__ X,
@@ -247,8 +246,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict_
   const int i = 2 * (int)(tid % mx) + pi;
   const int j = 2 * (int)((tid / mx) % my) + pj;
   const int k = 2 * (int)(tid / ((long long)mx * my)) + pk;
-  const int NX = nx + 1, NY = ny + 1, NXe = (NX + 1) >> 1;
-  const size_t N = (size_t)NX * NY * (nz + 1);
+  const int NX = nx + 1, NY = ny + 1;
+  const StLayout L = Dims{nx, ny, nz}.layout();
   double xe[3][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -263,38 +262,25 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict_
   // column b of K_e is K_e applied to the b-th unit vector
 #pragma unroll 1
   for (int b = 0; b < 8; ++b) {
-    double v[8] = {}, y[8] = {};
-    v[b] = 1.0;
+    double v[8], y[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      v[a] = (a == b) ? 1.0 : 0.0;
+      y[a] = 0.0;
+    }
     element_apply(Jg, v, c, y);
     const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
       const int o = (bx - ax + 1) + 3 * (by - ay + 1) + 9 * (bz - az + 1);
-      const size_t row = (size_t)(j + ay) * NX + ((size_t)(k + az) * NX * NY);
-      const size_t idx = (size_t)o * N + row + rowpos(i + ax, NXe);
+      const size_t idx = st_entry<double>(L.node(i + ax, j + ay, k + az), o);
       st[idx] += y[a];
     }
   }
 }
 
 // ---------------------------------------------------------------- element tiles
-
-enum TileMode { M_APPLY = 0, M_RESID = 1, M_RHS = 2, M_DIV = 3, M_ADJ = 4 };
-
-struct TileArgs {
-  const double* X;
-  const double* Y;
-  const double* Z;
-  const double* v;   // nodal field (apply, residual, divergence)
-  const double* f;   // right-hand side (residual)
-  const double* ue;  // element 3-vectors (rhs, divergence, adjoint scatter)
-  double* out;       // nodal output
-  double* partials;  // [channel][block] sums of squares over the free nodes
-  int nx, ny, nz;
-  double c[3];
-  Faces faces;
-};
 
 constexpr int TE = 16;       // element columns per tile side
 constexpr int TN = TE - 1;   // owned node columns per tile side
@@ -306,7 +292,7 @@ constexpr int TN = TE - 1;   // owned node columns per tile side
 // owner of a node then sums, in a fixed order, the lower contributions of the
 // current layer and the upper contributions of the layer below.
 template <int MODE>
-__global__ __launch_bounds__(256) void elem_tile_kernel(TileArgs A) {
+__device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by) {
   constexpr int CH = (MODE == M_DIV) ? 2 : 1;
   constexpr bool NODEV = (MODE == M_APPLY || MODE == M_RESID || MODE == M_DIV);
   constexpr bool ELEMV = (MODE == M_RHS || MODE == M_DIV || MODE == M_ADJ);
@@ -316,7 +302,7 @@ __global__ __launch_bounds__(256) void elem_tile_kernel(TileArgs A) {
   __shared__ double s_red[256];
 
   const int t = threadIdx.x, ex = t % TE, ey = t / TE;
-  const int i0 = blockIdx.x * TN, j0 = blockIdx.y * TN;
+  const int i0 = bx * TN, j0 = by * TN;
   const int ie = i0 - 1 + ex, je = j0 - 1 + ey;
   const int nx = A.nx, ny = A.ny, nz = A.nz, NX = nx + 1, NY = ny + 1;
   const bool ev = ie >= 0 && ie < nx && je >= 0 && je < ny;
@@ -449,7 +435,7 @@ __global__ __launch_bounds__(256) void elem_tile_kernel(TileArgs A) {
     node_out(nz, s);
   }
   if (A.partials) {
-    const int nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int nb = A.gx * A.gy, bid = by * A.gx + bx;
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
       __syncthreads();
@@ -462,20 +448,37 @@ __global__ __launch_bounds__(256) void elem_tile_kernel(TileArgs A) {
       if (t == 0) A.partials[(size_t)ch * nb + bid] = s_red[0];
     }
   }
+  __syncthreads();  // the LDS slots are reused by the next work item of a batched launch
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void elem_tile_kernel(TileJob A) {
+  elem_tile_body<MODE>(A, blockIdx.x, blockIdx.y);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void elem_tile_batched(WorkList W) {
+  for (int g = blockIdx.x; g < W.total; g += gridDim.x) {
+    int lo = 0, hi = W.njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (W.prefix[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    if (!W.active[W.member[lo]]) continue;
+    const TileJob& A = static_cast<const TileJob*>(W.jobs)[lo];
+    const int b = g - W.prefix[lo];
+    elem_tile_body<MODE>(A, b % A.gx, b / A.gx);
+  }
 }
 
 // ---------------------------------------------------------------- element-wise kernels
 
 // One thread per element column, marching up: recovery u = u0 + diag(c) grad lambda(0).
-__global__ __launch_bounds__(256) void recover_kernel(const double* __restrict__ X,
-                                                      const double* __restrict__ Y,
-                                                      const double* __restrict__ Z,
-                                                      const double* __restrict__ lam,
-                                                      const double* __restrict__ u0,
-                                                      double* __restrict__ u, int nx, int ny, int nz,
-                                                      double c0, double c1, double c2) {
-  const int ie = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int je = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void recover_body(const RecoverJob& R, int bx, int by) {
+  const int ie = bx * 64 + (threadIdx.x & 63);
+  const int je = by * 4 + (threadIdx.x >> 6);
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
   if (ie >= nx || je >= ny) return;
   const int NX = nx + 1, NY = ny + 1;
   const size_t plane = (size_t)NX * NY, E = (size_t)nx * ny * nz;
@@ -484,14 +487,13 @@ __global__ __launch_bounds__(256) void recover_kernel(const double* __restrict__
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const size_t n = (size_t)k * plane + (size_t)(je + (q >> 1)) * NX + ie + (q & 1);
-      xe[0][q + h] = X[n];
-      xe[1][q + h] = Y[n];
-      xe[2][q + h] = Z[n];
-      v[q + h] = lam[n];
+      xe[0][q + h] = R.X[n];
+      xe[1][q + h] = R.Y[n];
+      xe[2][q + h] = R.Z[n];
+      v[q + h] = R.lam[n];
     }
   };
   load(0, 0);
-  const double c[3] = {c0, c1, c2};
   for (int k = 0; k < nz; ++k) {
     load(k + 1, 4);
     double cj[3][3], r[3][3], g[3];
@@ -503,7 +505,7 @@ __global__ __launch_bounds__(256) void recover_kernel(const double* __restrict__
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double gx = (g[0] * r[0][d] + g[1] * r[1][d] + g[2] * r[2][d]) * idet;
-      u[d * E + e] = u0[d * E + e] + c[d] * gx;
+      R.u[d * E + e] = R.u0[d * E + e] + R.c[d] * gx;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -511,6 +513,25 @@ __global__ __launch_bounds__(256) void recover_kernel(const double* __restrict__
       for (int d = 0; d < 3; ++d) xe[d][q] = xe[d][q + 4];
       v[q] = v[q + 4];
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void recover_kernel(RecoverJob R) {
+  recover_body(R, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void recover_batched(WorkList W) {
+  for (int g = blockIdx.x; g < W.total; g += gridDim.x) {
+    int lo = 0, hi = W.njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (W.prefix[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    if (!W.active[W.member[lo]]) continue;
+    const RecoverJob& R = static_cast<const RecoverJob*>(W.jobs)[lo];
+    const int b = g - W.prefix[lo];
+    recover_body(R, b % R.gx, b / R.gx);
   }
 }
 
@@ -623,8 +644,16 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const double* __restrict__ v
   if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
 }
 
-TileArgs tile_args(const mcw_handle& h) {
-  TileArgs A{};
+dim3 tile_grid(const mcw_handle& h) {
+  return dim3((h.d.NX() + TN - 1) / TN, (h.d.NY() + TN - 1) / TN);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+TileJob tile_job(const mcw_handle& h) {
+  TileJob A{};
   A.X = h.X.as<double>();
   A.Y = h.Y.as<double>();
   A.Z = h.Z.as<double>();
@@ -635,16 +664,49 @@ TileArgs tile_args(const mcw_handle& h) {
   A.c[1] = h.c[1];
   A.c[2] = h.c[2];
   A.faces = h.faces;
+  const dim3 g = tile_grid(h);
+  A.gx = (int)g.x;
+  A.gy = (int)g.y;
   return A;
 }
 
-dim3 tile_grid(const mcw_handle& h) {
-  return dim3((h.d.NX() + TN - 1) / TN, (h.d.NY() + TN - 1) / TN);
+RecoverJob recover_job(const mcw_handle& h, const double* u0, const double* lam, double* u) {
+  RecoverJob R{};
+  R.X = h.X.as<double>();
+  R.Y = h.Y.as<double>();
+  R.Z = h.Z.as<double>();
+  R.lam = lam;
+  R.u0 = u0;
+  R.u = u;
+  R.nx = h.d.nx;
+  R.ny = h.d.ny;
+  R.nz = h.d.nz;
+  R.c[0] = h.c[0];
+  R.c[1] = h.c[1];
+  R.c[2] = h.c[2];
+  R.gx = (h.d.nx + 63) / 64;
+  R.gy = (h.d.ny + 3) / 4;
+  return R;
 }
 
-}  // namespace
+void launch_tile_batched(int mode, const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  const unsigned g = (unsigned)std::max(1, std::min(W.total, 4096));
+  switch (mode) {
+    case M_RESID: elem_tile_batched<M_RESID><<<g, 256, 0, s>>>(W); break;
+    case M_RHS: elem_tile_batched<M_RHS><<<g, 256, 0, s>>>(W); break;
+    case M_DIV: elem_tile_batched<M_DIV><<<g, 256, 0, s>>>(W); break;
+    default: throw Error{MCW_INVALID_ARG, "unsupported batched element mode"};
+  }
+  MCW_CHECK_LAUNCH();
+}
 
-// ---------------------------------------------------------------- launchers
+void launch_recover_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  const unsigned g = (unsigned)std::max(1, std::min(W.total, 8192));
+  recover_batched<<<g, 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
 
 void launch_geometry_check(const mcw_handle& h, long long* first_bad) {
   const long long E = (long long)h.d.nx * h.d.ny * h.d.nz;
@@ -672,7 +734,7 @@ void launch_assemble_stencil(const mcw_handle& h, double* st64) {
 // mode 0: out = K x (no boundary conditions); mode 1: out = f - K x at free nodes, 0 elsewhere.
 void launch_apply(const mcw_handle& h, const double* x, const double* f, double* out, int mode,
                   double* partials, size_t* n_part) {
-  TileArgs A = tile_args(h);
+  TileJob A = tile_job(h);
   A.v = x;
   A.f = f;
   A.out = out;
@@ -687,7 +749,7 @@ void launch_apply(const mcw_handle& h, const double* x, const double* f, double*
 }
 
 void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partials, size_t* n_part) {
-  TileArgs A = tile_args(h);
+  TileJob A = tile_job(h);
   A.ue = u0;
   A.out = f;
   A.partials = partials;
@@ -699,7 +761,7 @@ void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partia
 
 void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
                        double* partials, size_t* n_part) {
-  TileArgs A = tile_args(h);
+  TileJob A = tile_job(h);
   A.ue = u0;
   A.v = lam;
   A.out = D;
@@ -712,7 +774,7 @@ void launch_divergence(const mcw_handle& h, const double* u0, const double* lam,
 
 void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_lam, double* partials,
                             size_t* n_part) {
-  TileArgs A = tile_args(h);
+  TileJob A = tile_job(h);
   A.ue = g_u;
   A.out = g_lam;
   A.partials = partials;
@@ -723,10 +785,8 @@ void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_la
 }
 
 void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u) {
-  const dim3 g((h.d.nx + 63) / 64, (h.d.ny + 3) / 4);
-  recover_kernel<<<g, 256, 0, h.stream>>>(h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(),
-                                          lam, u0, u, h.d.nx, h.d.ny, h.d.nz, h.c[0], h.c[1],
-                                          h.c[2]);
+  const RecoverJob R = recover_job(h, u0, lam, u);
+  recover_kernel<<<dim3(R.gx, R.gy), 256, 0, h.stream>>>(R);
   MCW_CHECK_LAUNCH();
 }
 

@@ -57,17 +57,52 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// ---------------------------------------------------------------- stencil layout
+
+// 27-point stencils are stored per node as SW = 28 values (27 coefficients
+// and a zero pad), in 16-byte groups (4 floats or 2 doubles).  Nodes are
+// numbered plane by plane and row by row, with the even x indices of a row
+// first and then the odd ones, each half padded to a multiple of 64 nodes;
+// for every run of 64 consecutive node numbers the layout stores group 0 of
+// all 64 nodes, then group 1, and so on.  A wave of 64 lanes updating one
+// colour class of a row thus reads each coefficient group as one contiguous
+// 1 KB block, with a single address per lane and immediate offsets.
+constexpr int SW = 28;
+
+struct StLayout {
+  int NY = 0, NXeP = 0, rowlen = 0;
+  size_t nodes = 0;  // padded node count
+  __host__ __device__ size_t node(int i, int j, int k) const {
+    return ((size_t)k * NY + j) * rowlen + ((i & 1) ? NXeP + (i >> 1) : (i >> 1));
+  }
+};
+
+template <class T>
+__host__ __device__ inline size_t st_entry(size_t p, int o) {
+  constexpr int E = 16 / (int)sizeof(T);
+  constexpr int G = SW / E;
+  return ((p >> 6) * G + o / E) * (size_t)(64 * E) + (p & 63) * E + (o % E);
+}
+
 // ---------------------------------------------------------------- grid geometry
 
 // Node-grid dimensions of one level: NX = nx+1 nodes in x, etc.
 struct Dims {
   int nx, ny, nz;  // elements
-  int NX() const { return nx + 1; }
-  int NY() const { return ny + 1; }
-  int NZ() const { return nz + 1; }
-  size_t N() const { return (size_t)NX() * NY() * NZ(); }
-  // even x indices first in every stencil row: index of i inside its row
-  int NXe() const { return (NX() + 1) >> 1; }
+  __host__ __device__ int NX() const { return nx + 1; }
+  __host__ __device__ int NY() const { return ny + 1; }
+  __host__ __device__ int NZ() const { return nz + 1; }
+  __host__ __device__ size_t N() const { return (size_t)NX() * NY() * NZ(); }
+  // number of even x indices (they come first in every stencil row)
+  __host__ __device__ int NXe() const { return (NX() + 1) >> 1; }
+  __host__ __device__ StLayout layout() const {
+    StLayout L;
+    L.NY = NY();
+    L.NXeP = (NXe() + 63) & ~63;
+    L.rowlen = L.NXeP + ((NX() - NXe() + 63) & ~63);
+    L.nodes = (size_t)NZ() * NY() * L.rowlen;
+    return L;
+  }
 };
 
 // Free-node test: a node is fixed iff it lies on a face outside Gamma.
@@ -100,12 +135,101 @@ struct DirMapDev {
   const int* shi;
 };
 
+// ---------------------------------------------------------------- launch jobs
+
+// Arguments of one member's share of a launch.  Single solves launch one job
+// per kernel; a batch launches one persistent kernel per phase over the jobs
+// of all members (a flattened list of (job, block) work items).
+struct ColJob {  // smoother colour pass, residual
+  const void* st;
+  const void* f;
+  void* x;
+  void* r;
+  int NX, NY, NZ;
+  Faces fc;
+  int ci, cj, ncx, ncy;  // colour class and its column counts (smoother)
+  int tiles_x, nblocks;  // local grid of 64 x 4 column tiles
+};
+
+struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
+  const void* src;
+  void* dst;
+  int NXf, NYf, NZf, NXc, NYc, NZc;
+  Faces fc;
+  DirMapDev mx, my, mz;
+  int tiles_x, nblocks;
+};
+
+struct CoarseJob {  // e = K_L^-1 r on the free coarsest nodes
+  int n;
+  const double* inv;
+  const int* idx;
+  const void* r;
+  void* e;
+  int nblocks;
+};
+
+struct VecJob {  // fills, casts, lambda updates, zeroing of fixed nodes
+  void* p;          // output
+  const void* q;    // input
+  size_t n;
+  const double* scale;  // device scalar (casts / updates)
+  int NX, NY, NZ;       // zeroing of fixed nodes
+  Faces fc;
+  int nblocks;
+};
+
+struct SumJob {  // deterministic sum of `width` channels of n_part block partials
+  const double* partials;
+  size_t n_part;
+  int width;
+  double* out;
+};
+
+struct TileJob {  // element-tile kernels (matrix-free apply/residual, rhs, divergence, adjoint)
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const double* v;   // nodal field (apply, residual, divergence)
+  const double* f;   // right-hand side (residual)
+  const double* ue;  // element 3-vectors (rhs, divergence, adjoint scatter)
+  double* out;       // nodal output
+  double* partials;  // [channel][block] sums of squares over the free nodes
+  int nx, ny, nz;
+  double c[3];
+  Faces faces;
+  int gx, gy;        // tile grid
+};
+
+struct RecoverJob {  // u = u0 + diag(c) grad lambda at element centres
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const double* lam;
+  const double* u0;
+  double* u;
+  int nx, ny, nz;
+  double c[3];
+  int gx, gy;
+};
+
+// Work list of a batched launch: job j owns global blocks [prefix[j], prefix[j+1]);
+// member[j] indexes the per-member active flags.
+struct WorkList {
+  const void* jobs;
+  const int* prefix;
+  const int* member;
+  const int* active;
+  int njobs;
+  int total;
+};
+
 struct Level {
   Dims d;
   std::vector<int> keep_z;  // kept planes towards the next level (empty at the coarsest)
   int coarsen_h = 0;
-  DevBuf st64;              // 27 x N FP64 stencil, rows split even/odd in x
-  DevBuf st32;              // 27 x N FP32 stencil (FP32_REFINE), same layout
+  DevBuf st64;              // SW x N FP64 stencil (node-major, rows split even/odd in x)
+  DevBuf st32;              // SW x N FP32 stencil (FP32_REFINE), same layout
   DevBuf x, f, r;           // level vectors in V-cycle precision
   DirMap mx, my, mz;        // to the next coarser level
   DevBuf maps;              // device copies of the three DirMaps
@@ -166,6 +290,13 @@ void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const doubl
 void launch_check_finite(const mcw_handle& h, const double* v, size_t n, double* partials,
                          size_t* n_part);
 
+// element-tile modes and batched element launches
+enum TileMode { M_APPLY = 0, M_RESID = 1, M_RHS = 2, M_DIV = 3, M_ADJ = 4 };
+TileJob tile_job(const mcw_handle& h);
+RecoverJob recover_job(const mcw_handle& h, const double* u0, const double* lam, double* u);
+void launch_tile_batched(int mode, const WorkList& W, hipStream_t s);
+void launch_recover_batched(const WorkList& W, hipStream_t s);
+
 // Multigrid kernels (templated on the V-cycle precision)
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
@@ -189,12 +320,34 @@ void launch_rap(const Dims& df, const Dims& dc, const DirMapDev& mx, const DirMa
                 const DirMapDev& mz, const double* stf, double* stc, hipStream_t s);
 void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStream_t s);
 void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double, hipStream_t s);
-void launch_scale_to_f32(const Dims& d, const Faces& fc, const double* r, double scale, float* r32,
+// r32 = (float)(r * *scale); lam += e / *scale (scale is a device scalar)
+void launch_scale_to_f32(const Dims& d, const double* r, const double* scale, float* r32,
                          hipStream_t s);
-void launch_update_lambda(size_t n, const float* e, double inv_scale, double* lam, hipStream_t s);
+void launch_update_lambda(size_t n, const float* e, const double* scale, double* lam, hipStream_t s);
 void launch_axpy64(size_t n, double alpha, const double* x, double* y, hipStream_t s);
 void launch_zero_fixed(const Dims& d, const Faces& fc, double* v, hipStream_t s);
 void launch_sum_partials(const double* partials, size_t n_part, int width, double* out,
                          hipStream_t s);
+
+// Job builders (colour = -1: all columns)
+ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
+               int colour);
+XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
+                 const DirMapDev& my, const DirMapDev& mz, const void* src, void* dst,
+                 bool restriction);
+CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, void* e);
+VecJob vec_job(void* p, const void* q, size_t n, const double* scale);
+
+// Batched (persistent) launches over a work list of jobs
+template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s);
+template <class T> void launch_fill_batched(const WorkList& W, hipStream_t s);
+void launch_scale_batched(const WorkList& W, hipStream_t s);
+void launch_update_batched(const WorkList& W, hipStream_t s);
+void launch_zero_fixed_batched(const WorkList& W, hipStream_t s);
+void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s);
 
 }  // namespace mcw

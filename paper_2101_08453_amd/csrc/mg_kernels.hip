@@ -4,12 +4,17 @@
 // coarse operator K_c = P^T K P (eq. (7)), the coarsest direct solve, and the
 // precision casts of the FP32-inside-FP64 refinement.
 //
-// Stencil layout: 27 coefficient planes of N entries; coefficient o =
-// (di+1) + 3(dj+1) + 9(dk+1) of node (i,j,k) couples it to (i+di, j+dj, k+dk).
-// Within each grid row the entries are stored even-i first, then odd-i, so a
-// colour pass (every other i) reads contiguous memory.  Entries towards
-// nodes off the grid are exactly zero, so neighbour indices are clamped.
-// Node vectors are in natural x-fastest order.
+// Stencils use the grouped layout of StLayout / st_entry (mcw_internal.hpp);
+// coefficient o = (di+1) + 3(dj+1) + 9(dk+1) of node (i,j,k) couples it to
+// (i+di, j+dj, k+dk).  Entries towards nodes off the grid are exactly zero,
+// so neighbour indices are clamped.  Node vectors are in natural x-fastest
+// order.
+//
+// Every kernel is a device body run on one job's local block; the single
+// launches run it on blockIdx, the batched launches (several independent
+// problems in one persistent launch) walk a flattened (job, block) list.
+#include <algorithm>
+
 #include "mcw_internal.hpp"
 
 namespace mcw {
@@ -18,7 +23,32 @@ namespace {
 constexpr int BX = 64;  // columns per block along x (one wave)
 constexpr int BY = 4;   // rows of columns per block
 
-__device__ __forceinline__ int rowpos(int i, int NXe) { return (i & 1) ? NXe + (i >> 1) : (i >> 1); }
+__device__ __forceinline__ StLayout dev_layout(int NX, int NY) {
+  StLayout L;
+  L.NY = NY;
+  const int NXe = (NX + 1) >> 1;
+  L.NXeP = (NXe + 63) & ~63;
+  L.rowlen = L.NXeP + ((NX - NXe + 63) & ~63);
+  return L;
+}
+
+// The SW stencil values of node p, read as 16-byte groups that lie 1 KB apart.
+__device__ __forceinline__ void load_stencil(const float* __restrict__ st, size_t p, float a[SW]) {
+  const float4* v = reinterpret_cast<const float4*>(st) + (p >> 6) * (SW / 4) * 64 + (p & 63);
+#pragma unroll
+  for (int g = 0; g < SW / 4; ++g) {
+    const float4 t = v[g * 64];
+    a[4 * g] = t.x; a[4 * g + 1] = t.y; a[4 * g + 2] = t.z; a[4 * g + 3] = t.w;
+  }
+}
+__device__ __forceinline__ void load_stencil(const double* __restrict__ st, size_t p, double a[SW]) {
+  const double2* v = reinterpret_cast<const double2*>(st) + (p >> 6) * (SW / 2) * 64 + (p & 63);
+#pragma unroll
+  for (int g = 0; g < SW / 2; ++g) {
+    const double2 t = v[g * 64];
+    a[2 * g] = t.x; a[2 * g + 1] = t.y;
+  }
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so that neighbouring tiles share an L2.
@@ -27,6 +57,38 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, rem) + s;
 }
 
+// Job owning global work item g of a batched launch (prefix has njobs+1 entries).
+__device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Block-wide sum of one double per thread into *out (fixed tree, deterministic).
+__device__ __forceinline__ void block_sum_to(double v, double* s_red, double* out) {
+  s_red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s_red[0];
+  __syncthreads();
+}
+
+// Run BODY(job, local block) over the work list W of a batched launch.
+#define MCW_BATCHED_LOOP(JOBT, BODY)                                            \
+  for (int g = blockIdx.x; g < W.total; g += gridDim.x) {                       \
+    const int j = find_job(W.prefix, W.njobs, g);                               \
+    if (!W.active[W.member[j]]) continue;                                       \
+    const JOBT& J_ = static_cast<const JOBT*>(W.jobs)[j];                       \
+    BODY(J_, g - W.prefix[j]);                                                  \
+  }
+
 // ---------------------------------------------------------------- smoother
 
 // One colour pass: every column (i, j) with i = ci mod 2, j = cj mod 2 runs
@@ -34,26 +96,23 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // to other colours and are not changed during the pass; the value below is
 // this thread's own freshly updated one.
 template <class T>
-__global__ __launch_bounds__(256) void gs_pass_kernel(const T* __restrict__ st,
-                                                      const T* __restrict__ f, T* __restrict__ x,
-                                                      int NX, int NY, int NZ, Faces fc, int ci,
-                                                      int cj, int ncx, int ncy, int tiles_x,
-                                                      int nblocks) {
-  const int b = xcd_remap(blockIdx.x, nblocks);
-  const int ii = (b % tiles_x) * BX + (threadIdx.x % BX);
-  const int jj = (b / tiles_x) * BY + (threadIdx.x / BX);
-  if (ii >= ncx || jj >= ncy) return;
-  const int i = 2 * ii + ci, j = 2 * jj + cj;
-  if (fc.x_fixed(i, NX) || fc.y_fixed(j, NY)) return;
+__device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
+  const T* __restrict__ st = static_cast<const T*>(J.st);
+  const T* __restrict__ f = static_cast<const T*>(J.f);
+  T* __restrict__ x = static_cast<T*>(J.x);
+  const int NX = J.NX, NY = J.NY, NZ = J.NZ;
+  const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
+  const int jj = (b / J.tiles_x) * BY + (threadIdx.x / BX);
+  if (ii >= J.ncx || jj >= J.ncy) return;
+  const int i = 2 * ii + J.ci, j = 2 * jj + J.cj;
+  if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) return;
   const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
   const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
-  const int NXe = (NX + 1) >> 1;
+  const StLayout L = dev_layout(NX, NY);
   const int cols[9] = {jm * NX + im, jm * NX + i, jm * NX + ip, j * NX + im, j * NX + i,
                        j * NX + ip, jp * NX + im, jp * NX + i, jp * NX + ip};
   const size_t plane = (size_t)NX * NY;
-  const size_t N = plane * NZ;
-  const int cpos = j * NX + rowpos(i, NXe);
-  const int kf = fc.k_first(), kl = fc.k_last(NZ);
+  const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
   T xm[9], x0[9], xp[9];
   {
     const size_t pm = (size_t)(kf > 0 ? kf - 1 : 0) * plane, p0 = (size_t)kf * plane;
@@ -67,16 +126,17 @@ __global__ __launch_bounds__(256) void gs_pass_kernel(const T* __restrict__ st,
     const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
 #pragma unroll
     for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
-    const size_t cb = (size_t)k * plane + cpos;
+    T a[SW];
+    load_stencil(st, L.node(i, j, k), a);
     T s = f[(size_t)k * plane + cols[4]];
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       if (o == 13) continue;
       const int dk = o / 9, q = o % 9;
       const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
-      s -= st[(size_t)o * N + cb] * xv;
+      s -= a[o] * xv;
     }
-    const T xn = s / st[(size_t)13 * N + cb];
+    const T xn = s / a[13];
     x[(size_t)k * plane + cols[4]] = xn;
     x0[4] = xn;
 #pragma unroll
@@ -87,70 +147,88 @@ __global__ __launch_bounds__(256) void gs_pass_kernel(const T* __restrict__ st,
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
+  gs_pass_body<T>(J, xcd_remap(blockIdx.x, J.nblocks));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
+  MCW_BATCHED_LOOP(ColJob, gs_pass_body<T>)
+}
+
 // ---------------------------------------------------------------- residual
 
-template <class T, bool NORM>
-__global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ st,
-                                                       const T* __restrict__ x,
-                                                       const T* __restrict__ f, T* __restrict__ r,
-                                                       int NX, int NY, int NZ, Faces fc,
-                                                       int tiles_x, int nblocks,
-                                                       double* __restrict__ partials) {
-  __shared__ double s_red[256];
-  const int b = xcd_remap(blockIdx.x, nblocks);
-  const int i = (b % tiles_x) * BX + (threadIdx.x % BX);
-  const int j = (b / tiles_x) * BY + (threadIdx.x / BX);
+// r = f - K x at free nodes, 0 at fixed nodes; returns this thread's sum of r^2.
+template <class T>
+__device__ __forceinline__ double residual_body(const ColJob& J, int b) {
+  const T* __restrict__ st = static_cast<const T*>(J.st);
+  const T* __restrict__ x = static_cast<const T*>(J.x);
+  const T* __restrict__ f = static_cast<const T*>(J.f);
+  T* __restrict__ r = static_cast<T*>(J.r);
+  const int NX = J.NX, NY = J.NY, NZ = J.NZ;
+  const int i = (b % J.tiles_x) * BX + (threadIdx.x % BX);
+  const int j = (b / J.tiles_x) * BY + (threadIdx.x / BX);
   double acc = 0.0;
-  if (i < NX && j < NY) {
-    const size_t plane = (size_t)NX * NY, N = plane * NZ;
-    const bool colfree = !fc.x_fixed(i, NX) && !fc.y_fixed(j, NY);
-    const int kf = fc.k_first(), kl = fc.k_last(NZ);
-    const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
-    const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
-    const int NXe = (NX + 1) >> 1;
-    const int cols[9] = {jm * NX + im, jm * NX + i, jm * NX + ip, j * NX + im, j * NX + i,
-                         j * NX + ip, jp * NX + im, jp * NX + i, jp * NX + ip};
-    const int cpos = j * NX + rowpos(i, NXe);
-    T xm[9], x0[9], xp[9];
+  if (i >= NX || j >= NY) return acc;
+  const size_t plane = (size_t)NX * NY;
+  const int own = j * NX + i;
+  if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
+    for (int k = 0; k < NZ; ++k) r[(size_t)k * plane + own] = T(0);
+    return acc;
+  }
+  const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
+  const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
+  const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
+  const StLayout L = dev_layout(NX, NY);
+  const int cols[9] = {jm * NX + im, jm * NX + i, jm * NX + ip, j * NX + im, own,
+                       j * NX + ip, jp * NX + im, jp * NX + i, jp * NX + ip};
+  T xm[9], x0[9], xp[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    xm[q] = x[cols[q]];
+    x0[q] = xm[q];
+  }
+  // every k is computed (all loads are in range) so that the loads of a plane
+  // are issued together; rows of fixed planes are then set to zero
+  for (int k = 0; k < NZ; ++k) {
+    const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
+    T a[SW];
+    load_stencil(st, L.node(i, j, k), a);
+    T s = f[(size_t)k * plane + own];
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int dk = o / 9, q = o % 9;
+      const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
+      s -= a[o] * xv;
+    }
+    const T res = (k >= kf && k <= kl) ? s : T(0);
+    r[(size_t)k * plane + own] = res;
+    acc += (double)res * (double)res;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      xm[q] = x[cols[q]];
-      x0[q] = xm[q];
-    }
-    for (int k = 0; k < NZ; ++k) {
-      const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
-      T res = T(0);
-      if (colfree && k >= kf && k <= kl) {
-        const size_t cb = (size_t)k * plane + cpos;
-        T s = f[(size_t)k * plane + cols[4]];
-#pragma unroll
-        for (int o = 0; o < 27; ++o) {
-          const int dk = o / 9, q = o % 9;
-          const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
-          s -= st[(size_t)o * N + cb] * xv;
-        }
-        res = s;
-      }
-      r[(size_t)k * plane + cols[4]] = res;
-      if (NORM) acc += (double)res * (double)res;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        xm[q] = x0[q];
-        x0[q] = xp[q];
-      }
+      xm[q] = x0[q];
+      x0[q] = xp[q];
     }
   }
-  if (NORM) {
-    s_red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
-  }
+  return acc;
+}
+
+template <class T, bool NORM>
+__global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  const double acc = residual_body<T>(J, xcd_remap(blockIdx.x, J.nblocks));
+  if (NORM) block_sum_to(acc, s_red, &partials[blockIdx.x]);
+}
+
+template <class T>
+__device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T>(J, b); }
+
+template <class T>
+__global__ __launch_bounds__(256) void residual_batched(WorkList W) {
+  MCW_BATCHED_LOOP(ColJob, residual_nonorm<T>)
 }
 
 // ---------------------------------------------------------------- transfers
@@ -158,54 +236,62 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ st,
 // rc = P^T r: coarse node (I,J,K) gathers the fine nodes of its support with
 // weight 1 (the kept node) or 1/2 (a dropped neighbour), per direction.
 template <class T>
-__global__ __launch_bounds__(256) void restrict_kernel(const T* __restrict__ r, T* __restrict__ rc,
-                                                       int NXf, int NYf, int NXc, int NYc, int NZc,
-                                                       Faces fc, DirMapDev mx, DirMapDev my,
-                                                       DirMapDev mz) {
-  const int I = blockIdx.x * BX + (threadIdx.x % BX);
-  const int J = blockIdx.y * BY + (threadIdx.x / BX);
-  if (I >= NXc || J >= NYc) return;
-  const size_t pf = (size_t)NXf * NYf, pc = (size_t)NXc * NYc;
-  const bool colfree = !fc.x_fixed(I, NXc) && !fc.y_fixed(J, NYc);
-  const int kf = fc.k_first(), kl = fc.k_last(NZc);
-  const int xlo = mx.slo[I], xhi = mx.shi[I], xc = mx.ctr[I];
-  const int ylo = my.slo[J], yhi = my.shi[J], yc = my.ctr[J];
-  for (int K = 0; K < NZc; ++K) {
+__device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
+  const T* __restrict__ r = static_cast<const T*>(X.src);
+  T* __restrict__ rc = static_cast<T*>(X.dst);
+  const int I = (b % X.tiles_x) * BX + (threadIdx.x % BX);
+  const int J = (b / X.tiles_x) * BY + (threadIdx.x / BX);
+  if (I >= X.NXc || J >= X.NYc) return;
+  const size_t pf = (size_t)X.NXf * X.NYf, pc = (size_t)X.NXc * X.NYc;
+  const bool colfree = !X.fc.x_fixed(I, X.NXc) && !X.fc.y_fixed(J, X.NYc);
+  const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZc);
+  const int xlo = X.mx.slo[I], xhi = X.mx.shi[I], xc = X.mx.ctr[I];
+  const int ylo = X.my.slo[J], yhi = X.my.shi[J], yc = X.my.ctr[J];
+  for (int K = 0; K < X.NZc; ++K) {
     T v = T(0);
     if (colfree && K >= kf && K <= kl) {
-      const int zlo = mz.slo[K], zhi = mz.shi[K], zc = mz.ctr[K];
+      const int zlo = X.mz.slo[K], zhi = X.mz.shi[K], zc = X.mz.ctr[K];
       for (int pz = zlo; pz <= zhi; ++pz) {
         const T wz = pz == zc ? T(1) : T(0.5);
         for (int py = ylo; py <= yhi; ++py) {
           const T wy = py == yc ? wz : T(0.5) * wz;
-          const T* row = r + (size_t)pz * pf + (size_t)py * NXf;
+          const T* row = r + (size_t)pz * pf + (size_t)py * X.NXf;
           for (int px = xlo; px <= xhi; ++px) v += (px == xc ? wy : T(0.5) * wy) * row[px];
         }
       }
     }
-    rc[(size_t)K * pc + (size_t)J * NXc + I] = v;
+    rc[(size_t)K * pc + (size_t)J * X.NXc + I] = v;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void restrict_kernel(XferJob X) {
+  restrict_body<T>(X, blockIdx.x);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void restrict_batched(WorkList W) {
+  MCW_BATCHED_LOOP(XferJob, restrict_body<T>)
 }
 
 // x += P e: fine node p interpolates from coarse lo[p] and hi[p] per direction.
 template <class T>
-__global__ __launch_bounds__(256) void prolong_kernel(const T* __restrict__ e, T* __restrict__ x,
-                                                      int NXf, int NYf, int NZf, int NXc, int NYc,
-                                                      Faces fc, DirMapDev mx, DirMapDev my,
-                                                      DirMapDev mz, int tiles_x, int nblocks) {
-  const int b = xcd_remap(blockIdx.x, nblocks);
-  const int i = (b % tiles_x) * BX + (threadIdx.x % BX);
-  const int j = (b / tiles_x) * BY + (threadIdx.x / BX);
-  if (i >= NXf || j >= NYf) return;
-  if (fc.x_fixed(i, NXf) || fc.y_fixed(j, NYf)) return;
-  const size_t pf = (size_t)NXf * NYf, pc = (size_t)NXc * NYc;
-  const int kf = fc.k_first(), kl = fc.k_last(NZf);
-  const int xa = mx.lo[i], xb = mx.hi[i];
-  const int ya = my.lo[j], yb = my.hi[j];
+__device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
+  const T* __restrict__ e = static_cast<const T*>(X.src);
+  T* __restrict__ x = static_cast<T*>(X.dst);
+  const int i = (b % X.tiles_x) * BX + (threadIdx.x % BX);
+  const int j = (b / X.tiles_x) * BY + (threadIdx.x / BX);
+  if (i >= X.NXf || j >= X.NYf) return;
+  if (X.fc.x_fixed(i, X.NXf) || X.fc.y_fixed(j, X.NYf)) return;
+  const size_t pf = (size_t)X.NXf * X.NYf, pc = (size_t)X.NXc * X.NYc;
+  const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZf);
+  const int xa = X.mx.lo[i], xb = X.mx.hi[i];
+  const int ya = X.my.lo[j], yb = X.my.hi[j];
   const T wx = xa == xb ? T(1) : T(0.5), wxb = xa == xb ? T(0) : T(0.5);
   const T wy = ya == yb ? T(1) : T(0.5), wyb = ya == yb ? T(0) : T(0.5);
+  const int NXc = X.NXc;
   for (int k = kf; k <= kl; ++k) {
-    const int za = mz.lo[k], zb = mz.hi[k];
+    const int za = X.mz.lo[k], zb = X.mz.hi[k];
     const T wz = za == zb ? T(1) : T(0.5), wzb = za == zb ? T(0) : T(0.5);
     const T* pa = e + (size_t)za * pc;
     const T* pb = e + (size_t)zb * pc;
@@ -213,8 +299,18 @@ __global__ __launch_bounds__(256) void prolong_kernel(const T* __restrict__ e, T
       return wy * (wx * p[(size_t)ya * NXc + xa] + wxb * p[(size_t)ya * NXc + xb]) +
              wyb * (wx * p[(size_t)yb * NXc + xa] + wxb * p[(size_t)yb * NXc + xb]);
     };
-    x[(size_t)k * pf + (size_t)j * NXf + i] += wz * plane_val(pa) + wzb * plane_val(pb);
+    x[(size_t)k * pf + (size_t)j * X.NXf + i] += wz * plane_val(pa) + wzb * plane_val(pb);
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void prolong_kernel(XferJob X) {
+  prolong_body<T>(X, xcd_remap(blockIdx.x, X.nblocks));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void prolong_batched(WorkList W) {
+  MCW_BATCHED_LOOP(XferJob, prolong_body<T>)
 }
 
 // ---------------------------------------------------------------- Galerkin operator
@@ -229,9 +325,8 @@ __global__ __launch_bounds__(256) void rap_kernel(const double* __restrict__ stf
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= Nc) return;
   const int I = (int)(gid % NXc), J = (int)((gid / NXc) % NYc), K = (int)(gid / pc);
-  const size_t pf = (size_t)NXf * NYf, Nf = pf * NZf;
-  const int NXef = (NXf + 1) >> 1, NXec = (NXc + 1) >> 1;
-  const size_t outpos = (size_t)K * pc + (size_t)J * NXc + rowpos(I, NXec);
+  const StLayout Lf = dev_layout(NXf, NYf), Lc = dev_layout(NXc, NYc);
+  const size_t outpos = Lc.node(I, J, K);
   for (int o = 0; o < 27; ++o) {
     const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
     const int Bx = I + dx, By = J + dy, Bz = K + dz;
@@ -249,12 +344,12 @@ __global__ __launch_bounds__(256) void rap_kernel(const double* __restrict__ stf
               const double wy = wpy * (qy == my.ctr[By] ? 1.0 : 0.5);
               for (int px = mx.slo[I]; px <= mx.shi[I]; ++px) {
                 const double wpx = wy * (px == mx.ctr[I] ? 1.0 : 0.5);
-                const size_t prow = (size_t)pz * pf + (size_t)py * NXf + rowpos(px, NXef);
+                const size_t prow = Lf.node(px, py, pz);
                 const int qx0 = max(mx.slo[Bx], px - 1), qx1 = min(mx.shi[Bx], px + 1);
                 for (int qx = qx0; qx <= qx1; ++qx) {
                   const double w = wpx * (qx == mx.ctr[Bx] ? 1.0 : 0.5);
                   const int of = (qx - px + 1) + 3 * (qy - py + 1) + 9 * (qz - pz + 1);
-                  acc += w * stf[(size_t)of * Nf + prow];
+                  acc += w * stf[st_entry<double>(prow, of)];
                 }
               }
             }
@@ -262,37 +357,42 @@ __global__ __launch_bounds__(256) void rap_kernel(const double* __restrict__ stf
         }
       }
     }
-    stc[(size_t)o * Nc + outpos] = acc;
+    stc[st_entry<double>(outpos, o)] = acc;
   }
+  stc[st_entry<double>(outpos, 27)] = 0.0;
 }
 
 // FP32 copy of an FP64 stencil.  The off-diagonal entries are rounded, and
 // the diagonal is set to minus their (rounded) sum, so that constants stay in
 // the null space of the unconstrained FP32 operator as they are for K.
 __global__ __launch_bounds__(256) void round_stencil_kernel(const double* __restrict__ s64,
-                                                            float* __restrict__ s32, size_t N) {
+                                                            float* __restrict__ s32, int NX, int NY,
+                                                            size_t N) {
   const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
+  const StLayout L = dev_layout(NX, NY);
+  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
   double sum = 0.0;
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
     if (o == 13) continue;
-    const float v = (float)s64[(size_t)o * N + n];
-    s32[(size_t)o * N + n] = v;
+    const float v = (float)s64[st_entry<double>(p, o)];
+    s32[st_entry<float>(p, o)] = v;
     sum += (double)v;
   }
-  s32[(size_t)13 * N + n] = (float)(-sum);
+  s32[st_entry<float>(p, 13)] = (float)(-sum);
+  s32[st_entry<float>(p, 27)] = 0.f;
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T* __restrict__ out,
-                                                      int NX, size_t rows) {
+                                                      int NX, int NY, size_t N) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t N = rows * NX;
   if (gid >= N * 27) return;
-  const size_t o = gid / N, n = gid % N, row = n / NX;
-  const int i = (int)(n % NX);
-  out[gid] = s[o * N + row * NX + rowpos(i, (NX + 1) >> 1)];
+  const size_t o = gid / N, n = gid % N;
+  const StLayout L = dev_layout(NX, NY);
+  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+  out[gid] = s[st_entry<T>(p, (int)o)];
 }
 
 // ---------------------------------------------------------------- coarsest level
@@ -300,21 +400,74 @@ __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T
 // e[idx] = Kinv r[idx] for the free coarsest nodes (Kinv symmetric, so column
 // `row` is read with consecutive threads on consecutive addresses).
 template <class T>
-__global__ __launch_bounds__(256) void coarse_solve_kernel(int n, const double* __restrict__ inv,
-                                                           const int* __restrict__ idx,
-                                                           const T* __restrict__ r,
-                                                           T* __restrict__ e) {
-  extern __shared__ double rs[];
-  for (int t = threadIdx.x; t < n; t += blockDim.x) rs[t] = (double)r[idx[t]];
+__device__ __forceinline__ void coarse_body(const CoarseJob& C, int b, double* rs) {
+  const T* __restrict__ r = static_cast<const T*>(C.r);
+  T* __restrict__ e = static_cast<T*>(C.e);
+  const int n = C.n;
+  __syncthreads();  // rs may still be read by the previous work item
+  for (int t = threadIdx.x; t < n; t += blockDim.x) rs[t] = (double)r[C.idx[t]];
   __syncthreads();
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = b * blockDim.x + threadIdx.x;
   if (row >= n) return;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += inv[(size_t)j * n + row] * rs[j];
-  e[idx[row]] = (T)s;
+  for (int jj = 0; jj < n; ++jj) s += C.inv[(size_t)jj * n + row] * rs[jj];
+  e[C.idx[row]] = (T)s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void coarse_solve_kernel(CoarseJob C) {
+  extern __shared__ double rs[];
+  coarse_body<T>(C, blockIdx.x, rs);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void coarse_solve_batched(WorkList W) {
+  extern __shared__ double rs[];
+  for (int g = blockIdx.x; g < W.total; g += gridDim.x) {
+    const int j = find_job(W.prefix, W.njobs, g);
+    if (!W.active[W.member[j]]) continue;
+    coarse_body<T>(static_cast<const CoarseJob*>(W.jobs)[j], g - W.prefix[j], rs);
+  }
 }
 
 // ---------------------------------------------------------------- vectors
+
+// p = *q (a device scalar of type T), or 0 when q is null
+template <class T>
+__device__ __forceinline__ void fill_body(const VecJob& V, int b) {
+  T* __restrict__ p = static_cast<T*>(V.p);
+  const T v = V.q ? *static_cast<const T*>(V.q) : T(0);
+  for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256) p[i] = v;
+}
+
+// r32 = (float)(r * scale)
+__device__ __forceinline__ void scale_body(const VecJob& V, int b) {
+  const double* __restrict__ r = static_cast<const double*>(V.q);
+  float* __restrict__ r32 = static_cast<float*>(V.p);
+  const double s = *V.scale;
+  for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256)
+    r32[i] = (float)(r[i] * s);
+}
+
+// lam += (double)e / scale
+__device__ __forceinline__ void update_body(const VecJob& V, int b) {
+  const float* __restrict__ e = static_cast<const float*>(V.q);
+  double* __restrict__ lam = static_cast<double*>(V.p);
+  const double inv = 1.0 / *V.scale;
+  for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256)
+    lam[i] += (double)e[i] * inv;
+}
+
+__device__ __forceinline__ void zero_fixed_body(const VecJob& V, int b) {
+  double* __restrict__ v = static_cast<double*>(V.p);
+  const int NX = V.NX, NY = V.NY, NZ = V.NZ;
+  const size_t plane = (size_t)NX * NY, N = plane * NZ;
+  const int kf = V.fc.k_first(), kl = V.fc.k_last(NZ);
+  for (size_t n = (size_t)b * 256 + threadIdx.x; n < N; n += (size_t)V.nblocks * 256) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / plane);
+    if (V.fc.x_fixed(i, NX) || V.fc.y_fixed(j, NY) || k < kf || k > kl) v[n] = 0.0;
+  }
+}
 
 template <class T>
 __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, size_t n, T v) {
@@ -323,20 +476,17 @@ __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, size_t n, 
     p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void scale_to_f32_kernel(const double* __restrict__ r,
-                                                           double scale, float* __restrict__ r32,
-                                                           size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    r32[i] = (float)(r[i] * scale);
+template <class T>
+__global__ __launch_bounds__(256) void fill_batched(WorkList W) {
+  MCW_BATCHED_LOOP(VecJob, fill_body<T>)
 }
-
-__global__ __launch_bounds__(256) void update_lambda_kernel(const float* __restrict__ e,
-                                                            double inv_scale,
-                                                            double* __restrict__ lam, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    lam[i] += (double)e[i] * inv_scale;
+__global__ __launch_bounds__(256) void scale_kernel(VecJob V) { scale_body(V, blockIdx.x); }
+__global__ __launch_bounds__(256) void scale_batched(WorkList W) { MCW_BATCHED_LOOP(VecJob, scale_body) }
+__global__ __launch_bounds__(256) void update_kernel(VecJob V) { update_body(V, blockIdx.x); }
+__global__ __launch_bounds__(256) void update_batched(WorkList W) { MCW_BATCHED_LOOP(VecJob, update_body) }
+__global__ __launch_bounds__(256) void zero_fixed_kernel(VecJob V) { zero_fixed_body(V, blockIdx.x); }
+__global__ __launch_bounds__(256) void zero_fixed_batched(WorkList W) {
+  MCW_BATCHED_LOOP(VecJob, zero_fixed_body)
 }
 
 __global__ __launch_bounds__(256) void axpy64_kernel(double alpha, const double* __restrict__ x,
@@ -346,35 +496,25 @@ __global__ __launch_bounds__(256) void axpy64_kernel(double alpha, const double*
     y[i] += alpha * x[i];
 }
 
-__global__ __launch_bounds__(256) void zero_fixed_kernel(double* __restrict__ v, int NX, int NY,
-                                                         int NZ, Faces fc) {
-  const size_t plane = (size_t)NX * NY, N = plane * NZ;
-  const int kf = fc.k_first(), kl = fc.k_last(NZ);
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / plane);
-    if (fc.x_fixed(i, NX) || fc.y_fixed(j, NY) || k < kf || k > kl) v[n] = 0.0;
+// Deterministic final sum of per-block partials: thread t adds entries
+// t, t+256, ... in order, then a fixed tree.
+__device__ __forceinline__ void sum_body(const SumJob& S, double* s) {
+  for (int w = 0; w < S.width; ++w) {
+    double a = 0.0;
+    for (size_t i = threadIdx.x; i < S.n_part; i += 256) a += S.partials[(size_t)w * S.n_part + i];
+    block_sum_to(a, s, &S.out[w]);
   }
 }
 
-// Deterministic final sum of per-block partials: thread t adds entries
-// t, t+256, ... in order, then a fixed tree.
-__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partials,
-                                                           size_t n_part, int width,
-                                                           double* __restrict__ out) {
+__global__ __launch_bounds__(256) void sum_partials_kernel(SumJob S) {
   __shared__ double s[256];
-  for (int w = 0; w < width; ++w) {
-    double a = 0.0;
-    for (size_t i = threadIdx.x; i < n_part; i += 256) a += partials[(size_t)w * n_part + i];
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[w] = s[0];
-    __syncthreads();
-  }
+  sum_body(S, s);
+}
+
+// one block per job
+__global__ __launch_bounds__(256) void sum_partials_batched(const SumJob* __restrict__ jobs, int n) {
+  __shared__ double s[256];
+  for (int j = blockIdx.x; j < n; j += gridDim.x) sum_body(jobs[j], s);
 }
 
 unsigned grid_stride_blocks(size_t n) {
@@ -382,32 +522,85 @@ unsigned grid_stride_blocks(size_t n) {
   return (unsigned)(b < 16384 ? (b == 0 ? 1 : b) : 16384);
 }
 
-struct ColGrid {
-  int tiles_x, nblocks;
-};
-
-ColGrid col_grid(int ncx, int ncy) {
-  ColGrid g;
-  g.tiles_x = (ncx + BX - 1) / BX;
-  g.nblocks = g.tiles_x * ((ncy + BY - 1) / BY);
-  return g;
-}
+unsigned batched_grid(int total) { return (unsigned)std::max(1, std::min(total, 8192)); }
 
 }  // namespace
 
-// ---------------------------------------------------------------- launchers
+// ---------------------------------------------------------------- job builders
+
+ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
+               int colour) {
+  ColJob J{};
+  J.st = st;
+  J.f = f;
+  J.x = x;
+  J.r = r;
+  J.NX = d.NX();
+  J.NY = d.NY();
+  J.NZ = d.NZ();
+  J.fc = fc;
+  if (colour >= 0) {
+    static const int order[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    J.ci = order[colour][0];
+    J.cj = order[colour][1];
+    J.ncx = (d.NX() - J.ci + 1) / 2;
+    J.ncy = (d.NY() - J.cj + 1) / 2;
+  } else {
+    J.ncx = d.NX();
+    J.ncy = d.NY();
+  }
+  J.tiles_x = (J.ncx + BX - 1) / BX;
+  J.nblocks = std::max(0, J.tiles_x * ((J.ncy + BY - 1) / BY));
+  return J;
+}
+
+XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
+                 const DirMapDev& my, const DirMapDev& mz, const void* src, void* dst,
+                 bool restriction) {
+  XferJob X{};
+  X.src = src;
+  X.dst = dst;
+  X.NXf = df.NX();
+  X.NYf = df.NY();
+  X.NZf = df.NZ();
+  X.NXc = dc.NX();
+  X.NYc = dc.NY();
+  X.NZc = dc.NZ();
+  X.fc = fc;
+  X.mx = mx;
+  X.my = my;
+  X.mz = mz;
+  const int nxc = restriction ? X.NXc : X.NXf, nyc = restriction ? X.NYc : X.NYf;
+  X.tiles_x = (nxc + BX - 1) / BX;
+  X.nblocks = X.tiles_x * ((nyc + BY - 1) / BY);
+  return X;
+}
+
+CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, void* e) {
+  CoarseJob C{n, inv, idx, r, e, (n + 255) / 256};
+  return C;
+}
+
+VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
+  VecJob V{};
+  V.p = p;
+  V.q = q;
+  V.n = n;
+  V.scale = scale;
+  V.nblocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+  if (V.nblocks < 1) V.nblocks = 1;
+  return V;
+}
+
+// ---------------------------------------------------------------- single launches
 
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
                          hipStream_t s) {
-  static const int order[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
   for (int c = 0; c < 4; ++c) {
-    const int ci = order[c][0], cj = order[c][1];
-    const int ncx = (d.NX() - ci + 1) / 2, ncy = (d.NY() - cj + 1) / 2;
-    if (ncx <= 0 || ncy <= 0) continue;
-    const ColGrid g = col_grid(ncx, ncy);
-    gs_pass_kernel<T><<<g.nblocks, 256, 0, s>>>(st, f, x, d.NX(), d.NY(), d.NZ(), fc, ci, cj, ncx,
-                                                ncy, g.tiles_x, g.nblocks);
+    const ColJob J = col_job(d, fc, st, f, x, nullptr, c);
+    if (J.nblocks <= 0) continue;
+    gs_pass_kernel<T><<<J.nblocks, 256, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
 }
@@ -415,23 +608,20 @@ void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
                      double* partials, size_t* n_part, hipStream_t s) {
-  const ColGrid g = col_grid(d.NX(), d.NY());
+  const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1);
   if (partials)
-    residual_kernel<T, true><<<g.nblocks, 256, 0, s>>>(st, x, f, r, d.NX(), d.NY(), d.NZ(), fc,
-                                                       g.tiles_x, g.nblocks, partials);
+    residual_kernel<T, true><<<J.nblocks, 256, 0, s>>>(J, partials);
   else
-    residual_kernel<T, false><<<g.nblocks, 256, 0, s>>>(st, x, f, r, d.NX(), d.NY(), d.NZ(), fc,
-                                                        g.tiles_x, g.nblocks, nullptr);
+    residual_kernel<T, false><<<J.nblocks, 256, 0, s>>>(J, nullptr);
   MCW_CHECK_LAUNCH();
-  if (n_part) *n_part = g.nblocks;
+  if (n_part) *n_part = J.nblocks;
 }
 
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                      const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s) {
-  const dim3 g((dc.NX() + BX - 1) / BX, (dc.NY() + BY - 1) / BY);
-  restrict_kernel<T><<<g, 256, 0, s>>>(r, rc, df.NX(), df.NY(), dc.NX(), dc.NY(), dc.NZ(), fc, mx,
-                                       my, mz);
+  const XferJob X = xfer_job(df, dc, fc, mx, my, mz, r, rc, true);
+  restrict_kernel<T><<<X.nblocks, 256, 0, s>>>(X);
   MCW_CHECK_LAUNCH();
 }
 
@@ -439,17 +629,16 @@ template <class T>
 void launch_prolong_dims(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                          const DirMapDev& my, const DirMapDev& mz, const T* e, T* x,
                          hipStream_t s) {
-  const ColGrid g = col_grid(df.NX(), df.NY());
-  prolong_kernel<T><<<g.nblocks, 256, 0, s>>>(e, x, df.NX(), df.NY(), df.NZ(), dc.NX(), dc.NY(),
-                                              fc, mx, my, mz, g.tiles_x, g.nblocks);
+  const XferJob X = xfer_job(df, dc, fc, mx, my, mz, e, x, false);
+  prolong_kernel<T><<<X.nblocks, 256, 0, s>>>(X);
   MCW_CHECK_LAUNCH();
 }
 
 template <class T>
 void launch_coarse_solve(int n, const double* inv, const int* idx, const T* r, T* e,
                          hipStream_t s) {
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  coarse_solve_kernel<T><<<blocks, 256, (size_t)n * sizeof(double), s>>>(n, inv, idx, r, e);
+  const CoarseJob C = coarse_job(n, inv, idx, r, e);
+  coarse_solve_kernel<T><<<C.nblocks, 256, (size_t)n * sizeof(double), s>>>(C);
   MCW_CHECK_LAUNCH();
 }
 
@@ -470,34 +659,34 @@ void launch_rap(const Dims& df, const Dims& dc, const DirMapDev& mx, const DirMa
 
 void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStream_t s) {
   const size_t N = d.N();
-  round_stencil_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(st64, st32, N);
+  round_stencil_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(st64, st32, d.NX(), d.NY(), N);
   MCW_CHECK_LAUNCH();
 }
 
 void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double,
                             hipStream_t s) {
-  const size_t rows = (size_t)d.NY() * d.NZ();
-  const size_t tot = rows * d.NX() * 27;
-  const unsigned blocks = (unsigned)((tot + 255) / 256);
+  const size_t N = d.N();
+  const unsigned blocks = (unsigned)((N * 27 + 255) / 256);
   if (is_double)
     unsplit_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(st),
-                                                  static_cast<double*>(out), d.NX(), rows);
+                                                  static_cast<double*>(out), d.NX(), d.NY(), N);
   else
     unsplit_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(st),
-                                                 static_cast<float*>(out), d.NX(), rows);
+                                                 static_cast<float*>(out), d.NX(), d.NY(), N);
   MCW_CHECK_LAUNCH();
 }
 
-void launch_scale_to_f32(const Dims& d, const Faces& fc, const double* r, double scale, float* r32,
+void launch_scale_to_f32(const Dims& d, const double* r, const double* scale, float* r32,
                          hipStream_t s) {
-  (void)fc;
-  const size_t N = d.N();
-  scale_to_f32_kernel<<<grid_stride_blocks(N), 256, 0, s>>>(r, scale, r32, N);
+  const VecJob V = vec_job(r32, r, d.N(), scale);
+  scale_kernel<<<V.nblocks, 256, 0, s>>>(V);
   MCW_CHECK_LAUNCH();
 }
 
-void launch_update_lambda(size_t n, const float* e, double inv_scale, double* lam, hipStream_t s) {
-  update_lambda_kernel<<<grid_stride_blocks(n), 256, 0, s>>>(e, inv_scale, lam, n);
+void launch_update_lambda(size_t n, const float* e, const double* scale, double* lam,
+                          hipStream_t s) {
+  const VecJob V = vec_job(lam, e, n, scale);
+  update_kernel<<<V.nblocks, 256, 0, s>>>(V);
   MCW_CHECK_LAUNCH();
 }
 
@@ -507,13 +696,87 @@ void launch_axpy64(size_t n, double alpha, const double* x, double* y, hipStream
 }
 
 void launch_zero_fixed(const Dims& d, const Faces& fc, double* v, hipStream_t s) {
-  zero_fixed_kernel<<<grid_stride_blocks(d.N()), 256, 0, s>>>(v, d.NX(), d.NY(), d.NZ(), fc);
+  VecJob V = vec_job(v, nullptr, d.N(), nullptr);
+  V.NX = d.NX();
+  V.NY = d.NY();
+  V.NZ = d.NZ();
+  V.fc = fc;
+  zero_fixed_kernel<<<V.nblocks, 256, 0, s>>>(V);
   MCW_CHECK_LAUNCH();
 }
 
 void launch_sum_partials(const double* partials, size_t n_part, int width, double* out,
                          hipStream_t s) {
-  sum_partials_kernel<<<1, 256, 0, s>>>(partials, n_part, width, out);
+  const SumJob S{partials, n_part, width, out};
+  sum_partials_kernel<<<1, 256, 0, s>>>(S);
+  MCW_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------- batched launches
+
+template <class T>
+void launch_gs_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  gs_pass_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_residual_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  residual_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_restrict_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  restrict_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_prolong_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  prolong_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s) {
+  if (W.total <= 0) return;
+  coarse_solve_batched<T><<<batched_grid(W.total), 256, (size_t)max_n * sizeof(double), s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_fill_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  fill_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_scale_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  scale_batched<<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_update_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  update_batched<<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_zero_fixed_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  zero_fixed_batched<<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
+  if (n <= 0) return;
+  sum_partials_batched<<<(unsigned)n, 256, 0, s>>>(jobs, n);
   MCW_CHECK_LAUNCH();
 }
 
@@ -530,7 +793,13 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
                                        const T*, T*, hipStream_t);                              \
   template void launch_coarse_solve<T>(int, const double*, const int*, const T*, T*,            \
                                        hipStream_t);                                            \
-  template void launch_fill<T>(T*, size_t, T, hipStream_t);
+  template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
+  template void launch_gs_batched<T>(const WorkList&, hipStream_t);                             \
+  template void launch_residual_batched<T>(const WorkList&, hipStream_t);                       \
+  template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
+  template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \
+  template void launch_coarse_batched<T>(const WorkList&, int, hipStream_t);                    \
+  template void launch_fill_batched<T>(const WorkList&, hipStream_t);
 MCW_INST(float)
 MCW_INST(double)
 #undef MCW_INST

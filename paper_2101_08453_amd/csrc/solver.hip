@@ -3,6 +3,7 @@
 // drivers (plain FP64 multigrid, and FP32 V-cycles inside FP64 iterative
 // refinement), the adjoint, and the extern "C" entry points of mcwind.h.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
@@ -192,11 +193,12 @@ void factor_coarsest(mcw_handle& h) {
   Level& L = h.levels.back();
   const Dims d = L.d;
   const size_t N = d.N();
-  std::vector<double> st(27 * N);
+  const StLayout SL = d.layout();
+  std::vector<double> st(SW * SL.nodes);
   MCW_HIP(hipMemcpyAsync(st.data(), L.st64.p, st.size() * sizeof(double), hipMemcpyDeviceToHost,
                          h.stream));
   MCW_HIP(hipStreamSynchronize(h.stream));
-  const int NX = d.NX(), NY = d.NY(), NZ = d.NZ(), NXe = d.NXe();
+  const int NX = d.NX(), NY = d.NY(), NZ = d.NZ();
   std::vector<int> pos(N, -1), idx;
   const int k0 = h.faces.k_first(), k1 = h.faces.k_last(NZ);
   for (int k = 0; k < NZ; ++k)
@@ -214,13 +216,13 @@ void factor_coarsest(mcw_handle& h) {
   for (int r = 0; r < n; ++r) {
     const size_t nd = (size_t)idx[r];
     const int i = (int)(nd % NX), j = (int)((nd / NX) % NY), k = (int)(nd / ((size_t)NX * NY));
-    const size_t sp = (size_t)k * NX * NY + (size_t)j * NX + ((i & 1) ? NXe + (i >> 1) : (i >> 1));
+    const size_t sp = SL.node(i, j, k);
     for (int o = 0; o < 27; ++o) {
       const int ii = i + o % 3 - 1, jj = j + (o / 3) % 3 - 1, kk = k + o / 9 - 1;
       if (ii < 0 || ii >= NX || jj < 0 || jj >= NY || kk < 0 || kk >= NZ) continue;
       const int q = pos[(size_t)ii + (size_t)NX * (jj + (size_t)NY * kk)];
       if (q < 0) continue;
-      A[(size_t)r * n + q] += st[(size_t)o * N + sp];
+      A[(size_t)r * n + q] += st[st_entry<double>(sp, o)];
     }
   }
   for (int r = 0; r < n; ++r)
@@ -405,12 +407,16 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
       m = std::max(1, std::min(m, 12));
     }
     m = std::min(m, h.opt.max_cycles - pg.cycles);
+    // scale the residual by a power of two to O(1) before rounding it to FP32
     const double rms = std::sqrt(rr / nfree);
-    const double scale = std::ldexp(1.0, -std::ilogb(rms));
-    launch_scale_to_f32(h.d, h.faces, h.r64.as<double>(), scale, L0.f.as<float>(), h.stream);
+    h.host_scalars[7] = std::ldexp(1.0, -std::ilogb(rms));
+    double* scale_dev = h.scalars.as<double>() + 7;
+    MCW_HIP(hipMemcpyAsync(scale_dev, &h.host_scalars[7], sizeof(double), hipMemcpyHostToDevice,
+                           h.stream));
+    launch_scale_to_f32(h.d, h.r64.as<double>(), scale_dev, L0.f.as<float>(), h.stream);
     launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
     for (int c = 0; c < m; ++c) vcycle_f32(h);
-    launch_update_lambda(N, L0.x.as<float>(), 1.0 / scale, lam, h.stream);
+    launch_update_lambda(N, L0.x.as<float>(), scale_dev, lam, h.stream);
     pg.cycles += m;
     prev_m = m;
     prev_rel = pg.rel;
@@ -594,18 +600,18 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
   // a2 + a4: fine stencil by 2x2x2 Gauss, Galerkin coarse operators in FP64
   const bool f32 = opt.precision == MCW_FP32_REFINE;
   Level& L0 = h.levels[0];
-  L0.st64.alloc(27 * N * sizeof(double));
-  launch_fill<double>(L0.st64.as<double>(), 27 * N, 0.0, h.stream);
+  L0.st64.alloc(SW * h.d.layout().nodes * sizeof(double));
+  launch_fill<double>(L0.st64.as<double>(), SW * h.d.layout().nodes, 0.0, h.stream);
   launch_assemble_stencil(h, L0.st64.as<double>());
   for (size_t l = 0; l < h.levels.size(); ++l) {
     Level& L = h.levels[l];
     if (l + 1 < h.levels.size()) {
       Level& C = h.levels[l + 1];
-      C.st64.alloc(27 * C.d.N() * sizeof(double));
+      C.st64.alloc(SW * C.d.layout().nodes * sizeof(double));
       launch_rap(L.d, C.d, L.dmx, L.dmy, L.dmz, L.st64.as<double>(), C.st64.as<double>(), h.stream);
     }
     if (f32) {
-      L.st32.alloc(27 * L.d.N() * sizeof(float));
+      L.st32.alloc(SW * L.d.layout().nodes * sizeof(float));
       launch_round_stencil(L.d, L.st64.as<double>(), L.st32.as<float>(), h.stream);
       if (l + 1 < h.levels.size()) {
         MCW_HIP(hipStreamSynchronize(h.stream));
@@ -696,6 +702,462 @@ bool is_f32(const mcw_handle* h) { return h->opt.precision == MCW_FP32_REFINE; }
 
 }  // namespace
 
+// ---------------------------------------------------------------- batched solves
+
+// Per-member state of the refinement loop (mirrors iterate()).
+struct MemberState {
+  mcw_status st = MCW_OK;
+  bool active = false;
+  double fnorm = 0.0, rel = 0.0, prev_rel = -1.0, rho_est = 0.3;
+  int outer = 0, cycles = 0, prev_m = 0, stall = 0;
+  std::vector<double> hist;
+};
+
+// Device-side job tables of one batch: every phase has a work list over the
+// members that take part in it; all lists share one active-flag array.
+class Batch {
+ public:
+  Batch(std::vector<mcw_handle*> hs) : hs_(std::move(hs)), m_((int)hs_.size()), s_(hs_[0]->stream) {}
+  ~Batch() {
+    if (graph_) (void)hipGraphExecDestroy(graph_);
+    if (host_sums_) (void)hipHostFree(host_sums_);
+  }
+
+  void build() {
+    depth_ = 0;
+    for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
+    gs_.assign(depth_, {});
+    res_.assign(depth_, {});
+    restr_.assign(depth_, {});
+    fillx_.assign(depth_, {});
+    prol_.assign(depth_, {});
+    coarse_.assign(depth_, {});
+    for (int d = 0; d < depth_; ++d) {
+      std::vector<ColJob> gsj[4], rj;
+      std::vector<XferJob> rsj, pj;
+      std::vector<VecJob> fj;
+      std::vector<CoarseJob> cj;
+      std::vector<int> gsm[4], rm, rsm, pm, fm, cm;
+      for (int i = 0; i < m_; ++i) {
+        mcw_handle& h = *hs_[i];
+        const int L = (int)h.levels.size();
+        if (d >= L) continue;
+        Level& V = h.levels[d];
+        if (d == L - 1) {
+          max_coarse_ = std::max(max_coarse_, h.n_coarse);
+          cj.push_back(coarse_job(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(),
+                                  V.f.p, V.x.p));
+          cm.push_back(i);
+          continue;
+        }
+        Level& C = h.levels[d + 1];
+        for (int c = 0; c < 4; ++c) {
+          const ColJob J = col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, nullptr, c);
+          if (J.nblocks > 0) {
+            gsj[c].push_back(J);
+            gsm[c].push_back(i);
+          }
+        }
+        rj.push_back(col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, V.r.p, -1));
+        rm.push_back(i);
+        rsj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, V.r.p, C.f.p, true));
+        rsm.push_back(i);
+        pj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, C.x.p, V.x.p, false));
+        pm.push_back(i);
+        fj.push_back(vec_job(C.x.p, nullptr, C.d.N(), nullptr));
+        fm.push_back(i);
+      }
+      for (int c = 0; c < 4; ++c) gs_[d][c] = add(gsj[c], gsm[c]);
+      res_[d] = add(rj, rm);
+      restr_[d] = add(rsj, rsm);
+      prol_[d] = add(pj, pm);
+      fillx_[d] = add(fj, fm);
+      coarse_[d] = add(cj, cm);
+    }
+    // outer-loop phases over all members
+    std::vector<TileJob> rhs, res64, div;
+    std::vector<RecoverJob> rec;
+    std::vector<VecJob> zf, sc, f0, up;
+    std::vector<SumJob> s1, s2;
+    std::vector<int> all(m_);
+    for (int i = 0; i < m_; ++i) all[i] = i;
+    zero_slot_ = alloc_host(sizeof(double));  // float and double zero
+    scales_slot_ = alloc_host(m_ * sizeof(double));
+    sums_slot_ = alloc_host((size_t)m_ * 4 * sizeof(double));
+    for (int i = 0; i < m_; ++i) {
+      mcw_handle& h = *hs_[i];
+      const size_t N = h.d.N();
+      VecJob z = vec_job(nullptr, nullptr, N, nullptr);
+      z.NX = h.d.NX();
+      z.NY = h.d.NY();
+      z.NZ = h.d.NZ();
+      z.fc = h.faces;
+      zf.push_back(z);
+      TileJob A = tile_job(h);
+      A.f = h.f64.as<double>();
+      A.out = nullptr;
+      A.partials = h.partials.as<double>();
+      rhs.push_back(A);
+      res64.push_back(A);
+      div.push_back(A);
+      rec.push_back(recover_job(h, nullptr, nullptr, nullptr));
+      sc.push_back(vec_job(h.levels[0].f.p, h.r64.p, N, nullptr));
+      f0.push_back(vec_job(h.levels[0].x.p, nullptr, N, nullptr));
+      up.push_back(vec_job(nullptr, h.levels[0].x.p, N, nullptr));
+      s1.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 1, nullptr});
+      s2.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 2, nullptr});
+    }
+    zf_jobs_ = zf;
+    rhs_jobs_ = rhs;
+    res_jobs_ = res64;
+    div_jobs_ = div;
+    rec_jobs_ = rec;
+    sc_jobs_ = sc;
+    f0_jobs_ = f0;
+    up_jobs_ = up;
+    s1_jobs_ = s1;
+    s2_jobs_ = s2;
+    all_ = all;
+    // job tables whose pointers change per call are filled in solve(); reserve their space now
+    zf_ = add(zf, all);
+    rhs_ = add(rhs, all);
+    res64_ = add(res64, all);
+    div_ = add(div, all);
+    rec_ = add(rec, all);
+    sc_ = add(sc, all);
+    f0_ = add(f0, all);
+    up_ = add(up, all);
+    s1_off_ = add_raw(s1.data(), s1.size() * sizeof(SumJob));
+    s2_off_ = add_raw(s2.data(), s2.size() * sizeof(SumJob));
+    active_off_ = add_raw(nullptr, m_ * sizeof(int));
+    blob_.alloc(host_.size());
+    base_ = blob_.as<char>();
+    MCW_HIP(hipHostMalloc((void**)&host_sums_, (size_t)m_ * 4 * sizeof(double), hipHostMallocDefault));
+  }
+
+  // Solve all members; returns the first non-OK member status.
+  mcw_status solve(const double* const* u0, double* const* lam, double* const* u, mcw_info* infos) {
+    mcw_handle& h0 = *hs_[0];
+    const bool timing = true;
+    MCW_HIP(hipEventRecord(h0.ev[0], s_));
+    // per-call pointers
+    for (int i = 0; i < m_; ++i) {
+      zf_jobs_[i].p = lam[i];
+      rhs_jobs_[i].ue = u0[i];
+      rhs_jobs_[i].out = hs_[i]->f64.as<double>();
+      res_jobs_[i].v = lam[i];
+      res_jobs_[i].out = hs_[i]->r64.as<double>();
+      div_jobs_[i].ue = u0[i];
+      div_jobs_[i].v = lam[i];
+      div_jobs_[i].out = hs_[i]->t64.as<double>();
+      rec_jobs_[i].u0 = u0[i];
+      rec_jobs_[i].lam = lam[i];
+      rec_jobs_[i].u = u ? u[i] : nullptr;
+      sc_jobs_[i].scale = dev<double>(scales_slot_) + i;
+      up_jobs_[i].p = lam[i];
+      up_jobs_[i].scale = dev<double>(scales_slot_) + i;
+      s1_jobs_[i].out = dev<double>(sums_slot_) + 4 * i;
+      s2_jobs_[i].out = dev<double>(sums_slot_) + 4 * i;
+    }
+    put(zf_, zf_jobs_);
+    put(rhs_, rhs_jobs_);
+    put(res64_, res_jobs_);
+    put(div_, div_jobs_);
+    put(rec_, rec_jobs_);
+    put(sc_, sc_jobs_);
+    put(f0_, f0_jobs_);
+    put(up_, up_jobs_);
+    std::memcpy(&host_[s1_off_], s1_jobs_.data(), s1_jobs_.size() * sizeof(SumJob));
+    std::memcpy(&host_[s2_off_], s2_jobs_.data(), s2_jobs_.size() * sizeof(SumJob));
+    std::memset(&host_[zero_slot_], 0, sizeof(double));
+    std::vector<MemberState> ms(m_);
+    set_active(std::vector<int>(m_, 1));
+    upload();
+
+    launch_zero_fixed_batched(fix(zf_), s_);
+    launch_tile_batched(M_RHS, fix(rhs_), s_);
+    launch_sum_batched(dev<SumJob>(s1_off_), m_, s_);
+    fetch_sums();
+    std::vector<int> act(m_, 0);
+    for (int i = 0; i < m_; ++i) {
+      ms[i].fnorm = std::sqrt(host_sums_[4 * i]);
+      if (!std::isfinite(ms[i].fnorm)) {
+        ms[i].st = MCW_NONFINITE;
+      } else if (ms[i].fnorm == 0.0) {
+        launch_fill<double>(lam[i], hs_[i]->d.N(), 0.0, s_);
+      } else {
+        ms[i].active = true;
+        act[i] = 1;
+      }
+    }
+    MCW_HIP(hipEventRecord(h0.ev[1], s_));
+    const double tol = h0.opt.rtol;
+    for (;;) {
+      set_active(act);
+      upload_active();
+      launch_tile_batched(M_RESID, fix(res64_), s_);
+      launch_sum_batched(dev<SumJob>(s1_off_), m_, s_);
+      fetch_sums();
+      int want = 0;
+      for (int i = 0; i < m_; ++i) {
+        MemberState& S = ms[i];
+        if (!S.active) continue;
+        mcw_handle& h = *hs_[i];
+        const double rr = host_sums_[4 * i];
+        S.rel = std::sqrt(rr) / S.fnorm;
+        S.hist.push_back(S.rel);
+        ++S.outer;
+        if (!std::isfinite(S.rel)) { S.st = MCW_NONFINITE; S.active = false; }
+        else if (S.rel <= tol) { S.active = false; }
+        else if (S.cycles >= h.opt.max_cycles) { S.st = MCW_NOT_CONVERGED; S.active = false; }
+        if (S.active && S.prev_rel > 0.0 && S.prev_m > 0) {
+          const double red = S.rel / S.prev_rel;
+          if (red > 0.95) {
+            if (++S.stall >= 3) { S.st = MCW_NOT_CONVERGED; S.active = false; }
+          } else {
+            S.stall = 0;
+          }
+          S.rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / S.prev_m)));
+        }
+        if (!S.active) continue;
+        int mi = h.opt.inner_cycles;
+        if (mi <= 0) {
+          const double target = std::max(tol / S.rel, 3e-5);
+          mi = (int)std::ceil(std::log(target) / std::log(S.rho_est));
+          mi = std::max(1, std::min(mi, 12));
+        }
+        mi = std::min(mi, h.opt.max_cycles - S.cycles);
+        want = std::max(want, mi);
+        const double nfree = (double)std::max<size_t>(free_count(h.d, h.faces), 1);
+        reinterpret_cast<double*>(&host_[scales_slot_])[i] =
+            std::ldexp(1.0, -std::ilogb(std::sqrt(rr / nfree)));
+      }
+      for (int i = 0; i < m_; ++i) act[i] = ms[i].active ? 1 : 0;
+      if (want == 0) break;
+      set_active(act);
+      MCW_HIP(hipMemcpyAsync(base_ + scales_slot_, &host_[scales_slot_], m_ * sizeof(double),
+                             hipMemcpyHostToDevice, s_));
+      upload_active();
+      launch_scale_batched(fix(sc_), s_);
+      launch_fill_batched<float>(fix(f0_), s_);
+      for (int c = 0; c < want; ++c) vcycle();
+      launch_update_batched(fix(up_), s_);
+      for (int i = 0; i < m_; ++i)
+        if (ms[i].active) {
+          ms[i].cycles += want;
+          ms[i].prev_m = want;
+          ms[i].prev_rel = ms[i].rel;
+        }
+      MCW_HIP(hipStreamSynchronize(s_));  // host_ staging is rewritten next step
+    }
+    MCW_HIP(hipEventRecord(h0.ev[2], s_));
+    // recovery and divergence check for every member that has an iterate
+    std::vector<int> fin(m_, 0);
+    for (int i = 0; i < m_; ++i) fin[i] = (ms[i].st == MCW_OK || ms[i].st == MCW_NOT_CONVERGED) ? 1 : 0;
+    set_active(fin);
+    upload_active();
+    if (u) launch_recover_batched(fix(rec_), s_);
+    launch_tile_batched(M_DIV, fix(div_), s_);
+    launch_sum_batched(dev<SumJob>(s2_off_), m_, s_);
+    for (int i = 0; i < m_; ++i)
+      if (!fin[i] && u)
+        MCW_HIP(hipMemcpyAsync(u[i], u0[i], 3 * (size_t)hs_[i]->d.nx * hs_[i]->d.ny * hs_[i]->d.nz *
+                                               sizeof(double), hipMemcpyDeviceToDevice, s_));
+    fetch_sums();
+    MCW_HIP(hipEventRecord(h0.ev[3], s_));
+    MCW_HIP(hipEventSynchronize(h0.ev[3]));
+    float t_all = 0.f, t_rhs = 0.f, t_iter = 0.f, t_fin = 0.f;
+    if (timing) {
+      MCW_HIP(hipEventElapsedTime(&t_all, h0.ev[0], h0.ev[3]));
+      MCW_HIP(hipEventElapsedTime(&t_rhs, h0.ev[0], h0.ev[1]));
+      MCW_HIP(hipEventElapsedTime(&t_iter, h0.ev[1], h0.ev[2]));
+      MCW_HIP(hipEventElapsedTime(&t_fin, h0.ev[2], h0.ev[3]));
+    }
+    mcw_status first = MCW_OK;
+    for (int i = 0; i < m_; ++i) {
+      MemberState& S = ms[i];
+      if (S.st != MCW_OK && first == MCW_OK) first = S.st;
+      if (S.st == MCW_NOT_CONVERGED)
+        hs_[i]->last_error = "not converged: relative residual " + std::to_string(S.rel);
+      if (!infos) continue;
+      mcw_info* info = &infos[i];
+      std::memset(info, 0, sizeof(*info));
+      Progress pg;
+      pg.outer = S.outer;
+      pg.cycles = S.cycles;
+      pg.rel = S.rel;
+      pg.hist = S.hist;
+      fill_info(*hs_[i], pg, info);
+      info->f_norm = S.fnorm;
+      const double d0 = host_sums_[4 * i], d1 = host_sums_[4 * i + 1];
+      info->rel_divergence = d1 > 0.0 ? std::sqrt(d0 / d1) : std::sqrt(d0);
+      info->ms_total = t_all;
+      info->ms_rhs = t_rhs;
+      info->ms_cycles = t_iter;
+      info->ms_finish = t_fin;
+    }
+    return first;
+  }
+
+ private:
+  struct Slot {
+    size_t jobs = 0, prefix = 0, member = 0;
+    size_t bytes = 0;
+  };
+
+  template <class J>
+  WorkList add(const std::vector<J>& jobs, const std::vector<int>& members) {
+    std::vector<int> prefix(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j) prefix[j + 1] = prefix[j] + nblocks_of(jobs[j]);
+    WorkList W{};
+    const size_t jo = add_raw(jobs.data(), jobs.size() * sizeof(J));
+    const size_t po = add_raw(prefix.data(), prefix.size() * sizeof(int));
+    const size_t mo = add_raw(members.data(), members.size() * sizeof(int));
+    W.njobs = (int)jobs.size();
+    W.total = prefix.back();
+    // offsets are turned into device pointers once the blob exists
+    W.jobs = reinterpret_cast<const void*>(jo);
+    W.prefix = reinterpret_cast<const int*>(po);
+    W.member = reinterpret_cast<const int*>(mo);
+    return W;
+  }
+
+  static int nblocks_of(const ColJob& J) { return J.nblocks; }
+  static int nblocks_of(const XferJob& X) { return X.nblocks; }
+  static int nblocks_of(const CoarseJob& C) { return C.nblocks; }
+  static int nblocks_of(const VecJob& V) { return V.nblocks; }
+  static int nblocks_of(const TileJob& A) { return A.gx * A.gy; }
+  static int nblocks_of(const RecoverJob& R) { return R.gx * R.gy; }
+
+  size_t add_raw(const void* p, size_t bytes) {
+    const size_t off = (host_.size() + 255) & ~size_t(255);
+    host_.resize(off + bytes);
+    if (p && bytes) std::memcpy(&host_[off], p, bytes);
+    return off;
+  }
+  size_t alloc_host(size_t bytes) { return add_raw(nullptr, bytes); }
+
+  template <class T> T* dev(size_t off) { return reinterpret_cast<T*>(base_ + off); }
+
+  // device pointers of a work list built by add()
+  WorkList fix(const WorkList& W) {
+    WorkList R = W;
+    R.jobs = base_ + reinterpret_cast<size_t>(W.jobs);
+    R.prefix = reinterpret_cast<const int*>(base_ + reinterpret_cast<size_t>(W.prefix));
+    R.member = reinterpret_cast<const int*>(base_ + reinterpret_cast<size_t>(W.member));
+    R.active = reinterpret_cast<const int*>(base_ + active_off_);
+    return R;
+  }
+
+  template <class J>
+  void put(const WorkList& W, const std::vector<J>& jobs) {
+    std::memcpy(&host_[reinterpret_cast<size_t>(W.jobs)], jobs.data(), jobs.size() * sizeof(J));
+  }
+
+  void set_active(const std::vector<int>& a) {
+    std::memcpy(&host_[active_off_], a.data(), a.size() * sizeof(int));
+  }
+  void upload() {
+    MCW_HIP(hipMemcpyAsync(base_, host_.data(), host_.size(), hipMemcpyHostToDevice, s_));
+  }
+  void upload_active() {
+    MCW_HIP(hipMemcpyAsync(base_ + active_off_, &host_[active_off_], m_ * sizeof(int),
+                           hipMemcpyHostToDevice, s_));
+  }
+  void fetch_sums() {
+    MCW_HIP(hipMemcpyAsync(host_sums_, base_ + sums_slot_, (size_t)m_ * 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, s_));
+    MCW_HIP(hipStreamSynchronize(s_));
+  }
+
+  // one batched FP32 V-cycle over all members (depth-first over levels)
+  void vcycle_levels(int d) {
+    const int nu_pre = hs_[0]->opt.nu_pre, nu_post = hs_[0]->opt.nu_post;
+    launch_coarse_batched<float>(fix(coarse_[d]), std::max(max_coarse_, 1), s_);
+    if (res_[d].njobs == 0) return;
+    for (int s = 0; s < nu_pre; ++s)
+      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_);
+    launch_residual_batched<float>(fix(res_[d]), s_);
+    launch_restrict_batched<float>(fix(restr_[d]), s_);
+    launch_fill_batched<float>(fix(fillx_[d]), s_);
+    if (d + 1 < depth_) vcycle_levels(d + 1);
+    launch_prolong_batched<float>(fix(prol_[d]), s_);
+    for (int s = 0; s < nu_post; ++s)
+      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_);
+  }
+
+  void vcycle() {
+    if (!hs_[0]->opt.use_graph) {
+      vcycle_levels(0);
+      return;
+    }
+    if (!graph_) {
+      hipGraph_t g = nullptr;
+      MCW_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      try {
+        vcycle_levels(0);
+      } catch (...) {
+        (void)hipStreamEndCapture(s_, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      MCW_HIP(hipStreamEndCapture(s_, &g));
+      const hipError_t e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      MCW_HIP(e);
+    }
+    MCW_HIP(hipGraphLaunch(graph_, s_));
+  }
+
+  std::vector<mcw_handle*> hs_;
+  int m_;
+  hipStream_t s_;
+  int depth_ = 0, max_coarse_ = 0;
+  std::vector<std::array<WorkList, 4>> gs_;
+  std::vector<WorkList> res_, restr_, fillx_, prol_, coarse_;
+  WorkList zf_{}, rhs_{}, res64_{}, div_{}, rec_{}, sc_{}, f0_{}, up_{};
+  std::vector<VecJob> zf_jobs_, sc_jobs_, f0_jobs_, up_jobs_;
+  std::vector<TileJob> rhs_jobs_, res_jobs_, div_jobs_;
+  std::vector<RecoverJob> rec_jobs_;
+  std::vector<SumJob> s1_jobs_, s2_jobs_;
+  std::vector<int> all_;
+  size_t s1_off_ = 0, s2_off_ = 0, active_off_ = 0, zero_slot_ = 0, scales_slot_ = 0, sums_slot_ = 0;
+  std::vector<char> host_;
+  DevBuf blob_;
+  char* base_ = nullptr;
+  double* host_sums_ = nullptr;
+  hipGraphExec_t graph_ = nullptr;
+};
+
+mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u0,
+                            double* const* lambda, double* const* u, mcw_info* infos) {
+  if (m == 0) return MCW_OK;
+  for (int i = 0; i < m; ++i) {
+    if (!hs[i] || !u0[i] || !lambda[i]) Fail::arg("batch member " + std::to_string(i) + " has a null argument");
+    if (hs[i]->device != hs[0]->device) Fail::arg("batch members must share one device");
+    if (hs[i]->opt.precision != hs[0]->opt.precision) Fail::arg("batch members must share one precision");
+    if (hs[i]->opt.nu_pre != hs[0]->opt.nu_pre || hs[i]->opt.nu_post != hs[0]->opt.nu_post)
+      Fail::arg("batch members must share nu_pre and nu_post");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) Fail::arg("a handle appears twice in the batch");
+  }
+  if (hs[0]->opt.precision != MCW_FP32_REFINE) {
+    // plain FP64 handles are solved one after another
+    mcw_status first = MCW_OK;
+    for (int i = 0; i < m; ++i) {
+      const mcw_status s = solve_impl(*hs[i], u0[i], lambda[i], u ? u[i] : nullptr,
+                                      infos ? &infos[i] : nullptr);
+      if (s != MCW_OK && first == MCW_OK) first = s;
+    }
+    return first;
+  }
+  // members may run on their own streams: order them after the batch stream
+  for (int i = 1; i < m; ++i) MCW_HIP(hipStreamSynchronize(hs[i]->stream));
+  Batch b(std::vector<mcw_handle*>(hs, hs + m));
+  b.build();
+  return b.solve(u0, lambda, u, infos);
+}
+
 // ================================================================ C ABI
 
 extern "C" {
@@ -762,13 +1224,7 @@ mcw_status mcw_solve_batch(int32_t m, mcw_handle* const* hs, const double* const
     g_error = "bad batch arguments";
     return MCW_INVALID_ARG;
   }
-  mcw_status first = MCW_OK;
-  for (int i = 0; i < m; ++i) {
-    const mcw_status s = mcw_solve(hs[i], u0[i], lambda[i], u ? u[i] : nullptr,
-                                   infos ? &infos[i] : nullptr);
-    if (s != MCW_OK && first == MCW_OK) first = s;
-  }
-  return first;
+  return guarded(nullptr, [&] { return solve_batch_impl(m, hs, u0, lambda, u, infos); });
 }
 
 mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, float* dL_du0,
@@ -881,8 +1337,8 @@ mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out) {
         launch_unsplit_stencil(L.d, L.st64.p, out, 1, h->stream);
       } else if (l == 0) {
         DevBuf tmp;
-        tmp.alloc(27 * L.d.N() * sizeof(double));
-        launch_fill<double>(tmp.as<double>(), 27 * L.d.N(), 0.0, h->stream);
+        tmp.alloc(SW * L.d.layout().nodes * sizeof(double));
+        launch_fill<double>(tmp.as<double>(), SW * L.d.layout().nodes, 0.0, h->stream);
         launch_assemble_stencil(*h, tmp.as<double>());
         launch_unsplit_stencil(L.d, tmp.p, out, 1, h->stream);
         MCW_HIP(hipStreamSynchronize(h->stream));

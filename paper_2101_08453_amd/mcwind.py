@@ -346,8 +346,11 @@ class Grid:
         return x
 
 
-def solve_batch(grids, u0s, lams=None, want_u=True):
-    """Solve several problems together (mcw_solve_batch); returns (lams, us, infos, status)."""
+def solve_batch(grids, u0s, lams=None, want_u=True, check=True):
+    """Solve several problems together (mcw_solve_batch); returns (lams, us, infos, status).
+
+    With check=False a failing member does not raise: status names the first
+    failing member's status and each member's own outcome is in its info."""
     m = len(grids)
     if lams is None:
         lams = [g._node() for g in grids]
@@ -358,7 +361,7 @@ def solve_batch(grids, u0s, lams=None, want_u=True):
     pu = (P * m)(*[u.data_ptr() for u in us]) if want_u else None
     infos = (Info * m)()
     st = lib().mcw_solve_batch(m, hs, pu0, pl, pu, infos)
-    if st != MCW_OK:
+    if check and st != MCW_OK:
         raise MCWError(st, lib().mcw_last_error(None).decode())
     return lams, us, [infos[i].to_dict() for i in range(m)], STATUS_NAMES[st]
 
