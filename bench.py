@@ -86,35 +86,34 @@ def time_on_stream(stream, fn, reps):
 
 
 def kernel_table(g, stream, n_free):
-    """Fine-level kernels timed on the library's stream, with algorithmic bytes."""
-    import torch
+    """Fine-level kernels on the library's own buffers, HIP events on the library's
+    stream, with their algorithmic bytes."""
     shape = g.level_shape(0)
     N = int(np.prod(shape))
-    x32 = torch.randn(shape, dtype=torch.float32, device="cuda")
-    f32 = torch.randn(shape, dtype=torch.float32, device="cuda")
+    Nc = int(np.prod(g.level_shape(1)))
     out = {}
-    sweeps = 4
-    ms = time_on_stream(stream, lambda: g.smooth(0, x32, f32, sweeps=sweeps), 2) / (4 * sweeps)
-    # one colour pass updates a quarter of the free nodes: 27 FP32 coefficients, f, and x
-    # read and written once per node and sweep = 120 B per node per sweep
+
+    def timed(kernel, reps, launches_per_rep=1):
+        g.run_kernel(0, kernel, 1)  # warm
+        return time_on_stream(stream, lambda: g.run_kernel(0, kernel, reps), 1) / (reps * launches_per_rep)
+
+    # one colour pass updates a quarter of the free nodes: 27 FP32 coefficients and
+    # a pad (112 B), f, and x read and written once per node and sweep = 120 B
+    ms = timed("smooth", 8, 4)
     b = 120.0 * n_free / 4
     out["gs_colour_pass_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
-    ms = time_on_stream(stream, lambda: g.residual(0, x32, f32), 4)
-    b = (108.0 + 4 + 4 + 4) * N
+    ms = timed("residual", 4)
+    b = (112.0 + 4 + 4 + 4) * N
     out["residual_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
-    r = g.residual(0, x32, f32)
-    ms = time_on_stream(stream, lambda: g.restrict(0, r), 4)
-    Nc = int(np.prod(g.level_shape(1)))
+    ms = timed("restrict", 4)
     b = 4.0 * N + 4.0 * Nc
     out["restrict_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
-    e = torch.randn(g.level_shape(1), dtype=torch.float32, device="cuda")
-    ms = time_on_stream(stream, lambda: g.prolong(0, e, x32), 4)
+    ms = timed("prolong", 4)
     b = 8.0 * N + 4.0 * Nc
     out["prolong_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
-    lam = torch.randn(shape, dtype=torch.float64, device="cuda")
-    ms = time_on_stream(stream, lambda: g.apply_K(lam), 2)
-    # coordinates (24 B), x (8 B), y (8 B) per node; FP64 VALU bound
-    b = 40.0 * N
+    ms = timed("residual64", 2)
+    # coordinates (24 B), lambda, f and r (8 B each) per node; FP64 VALU bound
+    b = 48.0 * N
     out["apply_K_matfree_f64"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
     return out
 

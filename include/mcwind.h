@@ -104,6 +104,9 @@ typedef struct {
   int32_t coarse_direct_max;  /* largest coarsest-level unknown count (direct solve); default 1024, max 4096 */
   int32_t use_graph;          /* capture the FP32 V-cycle in a hipGraph and replay it; default 1 */
   int32_t verbose;            /* print setup and convergence lines to stderr; default 0 */
+  int32_t autotune;           /* time tile shapes of the colour pass and residual per level at
+                                 set-up and keep the fastest (cached in the JSON file named by
+                                 MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); default 1 */
 } mcw_options;
 
 #define MCW_MAX_LEVELS 24
@@ -232,6 +235,17 @@ mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e);
 
 /* One V-cycle on level 0 with x in/out, f in (V-cycle precision). */
 mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
+
+/* Run `reps` launches of one multigrid kernel on level l's own buffers (their
+ * current contents; no layout conversion, no allocation) and wait: kernel 0 =
+ * one Gauss-Seidel sweep (4 colour passes), 1 = residual, 2 = restriction to
+ * level l+1, 3 = prolongation from level l+1, 4 = FP64 matrix-free residual
+ * f - K lambda on the fine grid (l must be 0).  For timing and profiling. */
+mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps);
+
+/* Tile rows per block (blocks are 64 x rows columns) used on level l by the
+ * Gauss-Seidel colour pass and by the residual (host int32 outputs). */
+mcw_status mcw_tile_shape(const mcw_handle* h, int32_t l, int32_t* rows_smooth, int32_t* rows_residual);
 
 /* ---- errors ---- */
 const char* mcw_status_string(mcw_status s);

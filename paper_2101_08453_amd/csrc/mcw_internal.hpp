@@ -148,7 +148,8 @@ struct ColJob {  // smoother colour pass, residual
   int NX, NY, NZ;
   Faces fc;
   int ci, cj, ncx, ncy;  // colour class and its column counts (smoother)
-  int tiles_x, nblocks;  // local grid of 64 x 4 column tiles
+  int by;                // rows of 64-column tiles per block (block = 64 * by threads)
+  int tiles_x, nblocks;  // local grid of 64 x by column tiles
 };
 
 struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
@@ -230,10 +231,11 @@ struct Level {
   int coarsen_h = 0;
   DevBuf st64;              // SW x N FP64 stencil (node-major, rows split even/odd in x)
   DevBuf st32;              // SW x N FP32 stencil (FP32_REFINE), same layout
-  DevBuf x, f, r;           // level vectors in V-cycle precision
+  DevBuf x, f, r;           // level vectors in V-cycle precision, row-split order
   DirMap mx, my, mz;        // to the next coarser level
   DevBuf maps;              // device copies of the three DirMaps
   DirMapDev dmx{}, dmy{}, dmz{};
+  int by_gs = 4, by_res = 4;  // tuned tile rows of the colour pass and the residual
   double h1 = 0, h2 = 0;
   std::vector<double> h3;
 };
@@ -300,10 +302,10 @@ void launch_recover_batched(const WorkList& W, hipStream_t s);
 // Multigrid kernels (templated on the V-cycle precision)
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s);
+                         hipStream_t s, int by = 4);
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s);
+                     double* partials, size_t* n_part, hipStream_t s, int by = 4);
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                      const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s);
@@ -320,10 +322,14 @@ void launch_rap(const Dims& df, const Dims& dc, const DirMapDev& mx, const DirMa
                 const DirMapDev& mz, const double* stf, double* stc, hipStream_t s);
 void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStream_t s);
 void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double, hipStream_t s);
-// r32 = (float)(r * *scale); lam += e / *scale (scale is a device scalar)
+// r32 (row-split) = (float)(r * *scale); lam += e (row-split) / *scale (device scalar)
 void launch_scale_to_f32(const Dims& d, const double* r, const double* scale, float* r32,
                          hipStream_t s);
-void launch_update_lambda(size_t n, const float* e, const double* scale, double* lam, hipStream_t s);
+void launch_update_lambda(const Dims& d, const float* e, const double* scale, double* lam,
+                          hipStream_t s);
+// natural <-> row-split copies of level vectors
+template <class T>
+void launch_relayout(const Dims& d, const T* src, T* dst, bool to_split, hipStream_t s);
 void launch_axpy64(size_t n, double alpha, const double* x, double* y, hipStream_t s);
 void launch_zero_fixed(const Dims& d, const Faces& fc, double* v, hipStream_t s);
 void launch_sum_partials(const double* partials, size_t n_part, int width, double* out,
@@ -331,7 +337,7 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
 
 // Job builders (colour = -1: all columns)
 ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
-               int colour);
+               int colour, int by = 4);
 XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                  const DirMapDev& my, const DirMapDev& mz, const void* src, void* dst,
                  bool restriction);
@@ -339,8 +345,8 @@ CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, vo
 VecJob vec_job(void* p, const void* q, size_t n, const double* scale);
 
 // Batched (persistent) launches over a work list of jobs
-template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s);
-template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by = 4);
+template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by = 4);
 template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s);

@@ -7,8 +7,10 @@
 // Stencils use the grouped layout of StLayout / st_entry (mcw_internal.hpp);
 // coefficient o = (di+1) + 3(dj+1) + 9(dk+1) of node (i,j,k) couples it to
 // (i+di, j+dj, k+dk).  Entries towards nodes off the grid are exactly zero,
-// so neighbour indices are clamped.  Node vectors are in natural x-fastest
-// order.
+// so neighbour indices are clamped.  Caller-facing node vectors are in natural
+// x-fastest order in memory; the V-cycle's level vectors (x, f, r) use the same
+// row-split order as the stencils (even x indices of a row first, then the
+// odd ones, no padding), so a colour pass reads and writes them contiguously.
 //
 // Every kernel is a device body run on one job's local block; the single
 // launches run it on blockIdx, the batched launches (several independent
@@ -22,6 +24,9 @@ namespace {
 
 constexpr int BX = 64;  // columns per block along x (one wave)
 constexpr int BY = 4;   // rows of columns per block
+
+// Position of x index i inside its row in the row-split order of level vectors.
+__device__ __forceinline__ int sx(int i, int NXe) { return (i & 1) ? NXe + (i >> 1) : (i >> 1); }
 
 __device__ __forceinline__ StLayout dev_layout(int NX, int NY) {
   StLayout L;
@@ -102,15 +107,17 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
   T* __restrict__ x = static_cast<T*>(J.x);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
   const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
-  const int jj = (b / J.tiles_x) * BY + (threadIdx.x / BX);
+  const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   if (ii >= J.ncx || jj >= J.ncy) return;
   const int i = 2 * ii + J.ci, j = 2 * jj + J.cj;
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) return;
   const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
   const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
   const StLayout L = dev_layout(NX, NY);
-  const int cols[9] = {jm * NX + im, jm * NX + i, jm * NX + ip, j * NX + im, j * NX + i,
-                       j * NX + ip, jp * NX + im, jp * NX + i, jp * NX + ip};
+  const int NXe = (NX + 1) >> 1;
+  const int sm = sx(im, NXe), s0 = sx(i, NXe), sp = sx(ip, NXe);
+  const int cols[9] = {jm * NX + sm, jm * NX + s0, jm * NX + sp, j * NX + sm, j * NX + s0,
+                       j * NX + sp, jp * NX + sm, jp * NX + s0, jp * NX + sp};
   const size_t plane = (size_t)NX * NY;
   const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
   T xm[9], x0[9], xp[9];
@@ -167,12 +174,15 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ r = static_cast<T*>(J.r);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
-  const int i = (b % J.tiles_x) * BX + (threadIdx.x % BX);
-  const int j = (b / J.tiles_x) * BY + (threadIdx.x / BX);
+  // lanes follow the row-split order, so f, r and the stencil are read contiguously
+  const int qx = (b % J.tiles_x) * BX + (threadIdx.x % BX);
+  const int j = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   double acc = 0.0;
-  if (i >= NX || j >= NY) return acc;
+  if (qx >= NX || j >= NY) return acc;
   const size_t plane = (size_t)NX * NY;
-  const int own = j * NX + i;
+  const int NXe = (NX + 1) >> 1;
+  const int i = qx < NXe ? 2 * qx : 2 * (qx - NXe) + 1;
+  const int own = j * NX + qx;
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
     for (int k = 0; k < NZ; ++k) r[(size_t)k * plane + own] = T(0);
     return acc;
@@ -181,8 +191,9 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
   const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
   const StLayout L = dev_layout(NX, NY);
-  const int cols[9] = {jm * NX + im, jm * NX + i, jm * NX + ip, j * NX + im, own,
-                       j * NX + ip, jp * NX + im, jp * NX + i, jp * NX + ip};
+  const int sm = sx(im, NXe), sp = sx(ip, NXe);
+  const int cols[9] = {jm * NX + sm, jm * NX + sx(i, NXe), jm * NX + sp, j * NX + sm, own,
+                       j * NX + sp, jp * NX + sm, jp * NX + sx(i, NXe), jp * NX + sp};
   T xm[9], x0[9], xp[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -220,7 +231,12 @@ template <class T, bool NORM>
 __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restrict__ partials) {
   __shared__ double s_red[256];
   const double acc = residual_body<T>(J, xcd_remap(blockIdx.x, J.nblocks));
-  if (NORM) block_sum_to(acc, s_red, &partials[blockIdx.x]);
+  if (NORM) {
+    // blocks narrower than 256 threads: the missing lanes add zero
+    if (threadIdx.x == 0)
+      for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
+    block_sum_to(acc, s_red, &partials[blockIdx.x]);
+  }
 }
 
 template <class T>
@@ -247,6 +263,7 @@ __device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
   const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZc);
   const int xlo = X.mx.slo[I], xhi = X.mx.shi[I], xc = X.mx.ctr[I];
   const int ylo = X.my.slo[J], yhi = X.my.shi[J], yc = X.my.ctr[J];
+  const int NXef = (X.NXf + 1) >> 1, NXec = (X.NXc + 1) >> 1;
   for (int K = 0; K < X.NZc; ++K) {
     T v = T(0);
     if (colfree && K >= kf && K <= kl) {
@@ -256,11 +273,12 @@ __device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
         for (int py = ylo; py <= yhi; ++py) {
           const T wy = py == yc ? wz : T(0.5) * wz;
           const T* row = r + (size_t)pz * pf + (size_t)py * X.NXf;
-          for (int px = xlo; px <= xhi; ++px) v += (px == xc ? wy : T(0.5) * wy) * row[px];
+          for (int px = xlo; px <= xhi; ++px)
+            v += (px == xc ? wy : T(0.5) * wy) * row[sx(px, NXef)];
         }
       }
     }
-    rc[(size_t)K * pc + (size_t)J * X.NXc + I] = v;
+    rc[(size_t)K * pc + (size_t)J * X.NXc + sx(I, NXec)] = v;
   }
 }
 
@@ -279,15 +297,18 @@ template <class T>
 __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
   const T* __restrict__ e = static_cast<const T*>(X.src);
   T* __restrict__ x = static_cast<T*>(X.dst);
-  const int i = (b % X.tiles_x) * BX + (threadIdx.x % BX);
+  // lanes follow the row-split order of x, so the updates of a wave are contiguous
+  const int q = (b % X.tiles_x) * BX + (threadIdx.x % BX);
   const int j = (b / X.tiles_x) * BY + (threadIdx.x / BX);
-  if (i >= X.NXf || j >= X.NYf) return;
+  if (q >= X.NXf || j >= X.NYf) return;
+  const int NXef = (X.NXf + 1) >> 1, NXec = (X.NXc + 1) >> 1;
+  const int i = q < NXef ? 2 * q : 2 * (q - NXef) + 1;
   if (X.fc.x_fixed(i, X.NXf) || X.fc.y_fixed(j, X.NYf)) return;
   const size_t pf = (size_t)X.NXf * X.NYf, pc = (size_t)X.NXc * X.NYc;
   const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZf);
-  const int xa = X.mx.lo[i], xb = X.mx.hi[i];
+  const int xa = sx(X.mx.lo[i], NXec), xb = sx(X.mx.hi[i], NXec);
   const int ya = X.my.lo[j], yb = X.my.hi[j];
-  const T wx = xa == xb ? T(1) : T(0.5), wxb = xa == xb ? T(0) : T(0.5);
+  const T wx = X.mx.lo[i] == X.mx.hi[i] ? T(1) : T(0.5), wxb = X.mx.lo[i] == X.mx.hi[i] ? T(0) : T(0.5);
   const T wy = ya == yb ? T(1) : T(0.5), wyb = ya == yb ? T(0) : T(0.5);
   const int NXc = X.NXc;
   for (int k = kf; k <= kl; ++k) {
@@ -299,7 +320,7 @@ __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
       return wy * (wx * p[(size_t)ya * NXc + xa] + wxb * p[(size_t)ya * NXc + xb]) +
              wyb * (wx * p[(size_t)yb * NXc + xa] + wxb * p[(size_t)yb * NXc + xb]);
     };
-    x[(size_t)k * pf + (size_t)j * X.NXf + i] += wz * plane_val(pa) + wzb * plane_val(pb);
+    x[(size_t)k * pf + (size_t)j * X.NXf + q] += wz * plane_val(pa) + wzb * plane_val(pb);
   }
 }
 
@@ -440,22 +461,40 @@ __device__ __forceinline__ void fill_body(const VecJob& V, int b) {
   for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256) p[i] = v;
 }
 
-// r32 = (float)(r * scale)
+// Row-split position of natural node n of an NX-wide grid.
+__device__ __forceinline__ size_t split_pos(size_t n, int NX) {
+  const size_t row = n / NX;
+  return row * NX + sx((int)(n - row * NX), (NX + 1) >> 1);
+}
+
+// r32 (row-split) = (float)(r (natural) * scale)
 __device__ __forceinline__ void scale_body(const VecJob& V, int b) {
   const double* __restrict__ r = static_cast<const double*>(V.q);
   float* __restrict__ r32 = static_cast<float*>(V.p);
   const double s = *V.scale;
   for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256)
-    r32[i] = (float)(r[i] * s);
+    r32[split_pos(i, V.NX)] = (float)(r[i] * s);
 }
 
-// lam += (double)e / scale
+// lam (natural) += (double)e (row-split) / scale
 __device__ __forceinline__ void update_body(const VecJob& V, int b) {
   const float* __restrict__ e = static_cast<const float*>(V.q);
   double* __restrict__ lam = static_cast<double*>(V.p);
   const double inv = 1.0 / *V.scale;
   for (size_t i = (size_t)b * 256 + threadIdx.x; i < V.n; i += (size_t)V.nblocks * 256)
-    lam[i] += (double)e[i] * inv;
+    lam[i] += (double)e[split_pos(i, V.NX)] * inv;
+}
+
+// natural <-> row-split copies of a level vector
+template <class T>
+__global__ __launch_bounds__(256) void relayout_kernel(const T* __restrict__ src, T* __restrict__ dst,
+                                                       size_t n, int NX, int to_split) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = split_pos(i, NX);
+    if (to_split) dst[q] = src[i];
+    else dst[i] = src[q];
+  }
 }
 
 __device__ __forceinline__ void zero_fixed_body(const VecJob& V, int b) {
@@ -529,8 +568,9 @@ unsigned batched_grid(int total) { return (unsigned)std::max(1, std::min(total, 
 // ---------------------------------------------------------------- job builders
 
 ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
-               int colour) {
+               int colour, int by) {
   ColJob J{};
+  J.by = by;
   J.st = st;
   J.f = f;
   J.x = x;
@@ -550,7 +590,7 @@ ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, vo
     J.ncy = d.NY();
   }
   J.tiles_x = (J.ncx + BX - 1) / BX;
-  J.nblocks = std::max(0, J.tiles_x * ((J.ncy + BY - 1) / BY));
+  J.nblocks = std::max(0, J.tiles_x * ((J.ncy + by - 1) / by));
   return J;
 }
 
@@ -596,23 +636,23 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s) {
+                         hipStream_t s, int by) {
   for (int c = 0; c < 4; ++c) {
-    const ColJob J = col_job(d, fc, st, f, x, nullptr, c);
+    const ColJob J = col_job(d, fc, st, f, x, nullptr, c, by);
     if (J.nblocks <= 0) continue;
-    gs_pass_kernel<T><<<J.nblocks, 256, 0, s>>>(J);
+    gs_pass_kernel<T><<<J.nblocks, BX * by, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
 }
 
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s) {
-  const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1);
+                     double* partials, size_t* n_part, hipStream_t s, int by) {
+  const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
   if (partials)
-    residual_kernel<T, true><<<J.nblocks, 256, 0, s>>>(J, partials);
+    residual_kernel<T, true><<<J.nblocks, BX * by, 0, s>>>(J, partials);
   else
-    residual_kernel<T, false><<<J.nblocks, 256, 0, s>>>(J, nullptr);
+    residual_kernel<T, false><<<J.nblocks, BX * by, 0, s>>>(J, nullptr);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = J.nblocks;
 }
@@ -676,16 +716,26 @@ void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_dou
   MCW_CHECK_LAUNCH();
 }
 
+template <class T>
+void launch_relayout(const Dims& d, const T* src, T* dst, bool to_split, hipStream_t s) {
+  relayout_kernel<T><<<grid_stride_blocks(d.N()), 256, 0, s>>>(src, dst, d.N(), d.NX(), to_split ? 1 : 0);
+  MCW_CHECK_LAUNCH();
+}
+template void launch_relayout<float>(const Dims&, const float*, float*, bool, hipStream_t);
+template void launch_relayout<double>(const Dims&, const double*, double*, bool, hipStream_t);
+
 void launch_scale_to_f32(const Dims& d, const double* r, const double* scale, float* r32,
                          hipStream_t s) {
-  const VecJob V = vec_job(r32, r, d.N(), scale);
+  VecJob V = vec_job(r32, r, d.N(), scale);
+  V.NX = d.NX();
   scale_kernel<<<V.nblocks, 256, 0, s>>>(V);
   MCW_CHECK_LAUNCH();
 }
 
-void launch_update_lambda(size_t n, const float* e, const double* scale, double* lam,
+void launch_update_lambda(const Dims& d, const float* e, const double* scale, double* lam,
                           hipStream_t s) {
-  const VecJob V = vec_job(lam, e, n, scale);
+  VecJob V = vec_job(lam, e, d.N(), scale);
+  V.NX = d.NX();
   update_kernel<<<V.nblocks, 256, 0, s>>>(V);
   MCW_CHECK_LAUNCH();
 }
@@ -715,16 +765,16 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
 // ---------------------------------------------------------------- batched launches
 
 template <class T>
-void launch_gs_batched(const WorkList& W, hipStream_t s) {
+void launch_gs_batched(const WorkList& W, hipStream_t s, int by) {
   if (W.total <= 0) return;
-  gs_pass_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  gs_pass_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   MCW_CHECK_LAUNCH();
 }
 
 template <class T>
-void launch_residual_batched(const WorkList& W, hipStream_t s) {
+void launch_residual_batched(const WorkList& W, hipStream_t s, int by) {
   if (W.total <= 0) return;
-  residual_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  residual_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   MCW_CHECK_LAUNCH();
 }
 
@@ -782,9 +832,9 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 
 #define MCW_INST(T)                                                                             \
   template void launch_smooth_sweep<T>(const Dims&, const Faces&, const T*, const T*, T*,       \
-                                       hipStream_t);                                            \
+                                       hipStream_t, int);                                       \
   template void launch_residual<T>(const Dims&, const Faces&, const T*, const T*, const T*, T*, \
-                                   double*, size_t*, hipStream_t);                              \
+                                   double*, size_t*, hipStream_t, int);                         \
   template void launch_restrict<T>(const Dims&, const Dims&, const Faces&, const DirMapDev&,    \
                                    const DirMapDev&, const DirMapDev&, const T*, T*,            \
                                    hipStream_t);                                                \
@@ -794,8 +844,8 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_coarse_solve<T>(int, const double*, const int*, const T*, T*,            \
                                        hipStream_t);                                            \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
-  template void launch_gs_batched<T>(const WorkList&, hipStream_t);                             \
-  template void launch_residual_batched<T>(const WorkList&, hipStream_t);                       \
+  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int);                        \
+  template void launch_residual_batched<T>(const WorkList&, hipStream_t, int);                  \
   template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
   template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \
   template void launch_coarse_batched<T>(const WorkList&, int, hipStream_t);                    \

@@ -8,7 +8,12 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <sstream>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "mcw_internal.hpp"
 
@@ -199,7 +204,7 @@ void factor_coarsest(mcw_handle& h) {
                          h.stream));
   MCW_HIP(hipStreamSynchronize(h.stream));
   const int NX = d.NX(), NY = d.NY(), NZ = d.NZ();
-  std::vector<int> pos(N, -1), idx;
+  std::vector<int> pos(N, -1), idx, split_idx;  // natural and row-split node numbers
   const int k0 = h.faces.k_first(), k1 = h.faces.k_last(NZ);
   for (int k = 0; k < NZ; ++k)
     for (int j = 0; j < NY; ++j)
@@ -208,6 +213,8 @@ void factor_coarsest(mcw_handle& h) {
         const size_t n = (size_t)i + (size_t)NX * (j + (size_t)NY * k);
         pos[n] = (int)idx.size();
         idx.push_back((int)n);
+        const int NXe = (NX + 1) >> 1;
+        split_idx.push_back((int)(n - i + ((i & 1) ? NXe + (i >> 1) : (i >> 1))));
       }
   const int n = (int)idx.size();
   h.n_coarse = n;
@@ -269,10 +276,10 @@ void factor_coarsest(mcw_handle& h) {
     }
   }
   h.coarse_inv.alloc(inv.size() * sizeof(double));
-  h.coarse_idx.alloc(idx.size() * sizeof(int));
+  h.coarse_idx.alloc(split_idx.size() * sizeof(int));
   MCW_HIP(hipMemcpyAsync(h.coarse_inv.p, inv.data(), inv.size() * sizeof(double),
                          hipMemcpyHostToDevice, h.stream));
-  MCW_HIP(hipMemcpyAsync(h.coarse_idx.p, idx.data(), idx.size() * sizeof(int),
+  MCW_HIP(hipMemcpyAsync(h.coarse_idx.p, split_idx.data(), split_idx.size() * sizeof(int),
                          hipMemcpyHostToDevice, h.stream));
   MCW_HIP(hipStreamSynchronize(h.stream));
 }
@@ -303,14 +310,14 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
     return;
   }
   const T* st = stencil_of<T>(L);
-  for (int s = 0; s < h.opt.nu_pre; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream);
-  launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream);
+  for (int s = 0; s < h.opt.nu_pre; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs);
+  launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res);
   Level& C = h.levels[l + 1];
   launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
   launch_fill<T>(C.x.as<T>(), C.d.N(), T(0), h.stream);
   vcycle<T>(h, l + 1, C.x.as<T>(), C.f.as<T>());
   launch_prolong_dims<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, C.x.as<T>(), x, h.stream);
-  for (int s = 0; s < h.opt.nu_post; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream);
+  for (int s = 0; s < h.opt.nu_post; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs);
 }
 
 // One FP32 V-cycle on the level-0 buffers, replayed from a hipGraph when enabled.
@@ -356,20 +363,28 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
   size_t np = 0;
   double rr = 0.0;
   if (h.opt.precision == MCW_FP64) {
+    // the V-cycle works on row-split copies of lambda and f
+    double* x0 = L0.x.as<double>();
+    double* f0 = L0.f.as<double>();
+    launch_relayout<double>(h.d, lam, x0, true, h.stream);
+    launch_relayout<double>(h.d, h.f64.as<double>(), f0, true, h.stream);
+    mcw_status st = MCW_OK;
     for (;;) {
-      launch_residual<double>(L0.d, h.faces, L0.st64.as<double>(), lam, h.f64.as<double>(),
-                              h.r64.as<double>(), h.partials.as<double>(), &np, h.stream);
+      launch_residual<double>(L0.d, h.faces, L0.st64.as<double>(), x0, f0, L0.r.as<double>(),
+                              h.partials.as<double>(), &np, h.stream, L0.by_res);
       reduce_to_host(h, np, 1, &rr);
       pg.rel = std::sqrt(rr) / fnorm;
       pg.hist.push_back(pg.rel);
       ++pg.outer;
       logf(h, "fp64 cycle %d  rel residual %.3e", pg.cycles, pg.rel);
-      if (!std::isfinite(pg.rel)) return MCW_NONFINITE;
-      if (pg.rel <= tol) return MCW_OK;
-      if (pg.cycles >= h.opt.max_cycles) return MCW_NOT_CONVERGED;
-      vcycle<double>(h, 0, lam, h.f64.as<double>());
+      if (!std::isfinite(pg.rel)) { st = MCW_NONFINITE; break; }
+      if (pg.rel <= tol) break;
+      if (pg.cycles >= h.opt.max_cycles) { st = MCW_NOT_CONVERGED; break; }
+      vcycle<double>(h, 0, x0, f0);
       ++pg.cycles;
     }
+    launch_relayout<double>(h.d, x0, lam, false, h.stream);
+    return st;
   }
   // FP32 V-cycles inside FP64 iterative refinement
   double rho_est = 0.3, prev_rel = -1.0;
@@ -416,7 +431,7 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     launch_scale_to_f32(h.d, h.r64.as<double>(), scale_dev, L0.f.as<float>(), h.stream);
     launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
     for (int c = 0; c < m; ++c) vcycle_f32(h);
-    launch_update_lambda(N, L0.x.as<float>(), scale_dev, lam, h.stream);
+    launch_update_lambda(h.d, L0.x.as<float>(), scale_dev, lam, h.stream);
     pg.cycles += m;
     prev_m = m;
     prev_rel = pg.rel;
@@ -490,6 +505,117 @@ mcw_status solve_impl(mcw_handle& h, const double* u0, double* lam, double* u, m
     MCW_HIP(hipEventElapsedTime(&t, h.ev[2], h.ev[3])); info->ms_finish = t;
   }
   return st;
+}
+
+// ---------------------------------------------------------------- tile-shape autotuner
+
+// Cache of tuned tile rows, one `"key": rows` pair per line of a JSON object.
+class TuneCache {
+ public:
+  TuneCache() {
+    const char* env = std::getenv("MCW_TUNE_CACHE");
+    if (env && *env) {
+      path_ = env;
+    } else if (const char* home = std::getenv("HOME")) {
+      const std::string dir = std::string(home) + "/.cache/mcwind";
+      (void)mkdir((std::string(home) + "/.cache").c_str(), 0755);
+      (void)mkdir(dir.c_str(), 0755);
+      path_ = dir + "/tune.json";
+    }
+    std::ifstream in(path_);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find(':', b + 1);
+      if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+      m_[line.substr(a + 1, b - a - 1)] = std::atoi(line.c_str() + c + 1);
+    }
+  }
+  bool get(const std::string& k, int& v) const {
+    auto it = m_.find(k);
+    if (it == m_.end()) return false;
+    v = it->second;
+    return true;
+  }
+  void put(const std::string& k, int v) {
+    m_[k] = v;
+    dirty_ = true;
+  }
+  void save() {
+    if (!dirty_ || path_.empty()) return;
+    const std::string tmp = path_ + ".tmp" + std::to_string(getpid());
+    {
+      std::ofstream out(tmp);
+      if (!out) return;
+      out << "{\n";
+      size_t i = 0;
+      for (auto& kv : m_) out << "  \"" << kv.first << "\": " << kv.second << (++i < m_.size() ? ",\n" : "\n");
+      out << "}\n";
+    }
+    (void)std::rename(tmp.c_str(), path_.c_str());
+  }
+
+ private:
+  std::string path_;
+  std::map<std::string, int> m_;
+  bool dirty_ = false;
+};
+
+// Time rows-per-block candidates of the colour pass and the residual on every
+// level large enough for the shape to matter, on the level's own buffers.
+template <class T>
+void autotune_levels(mcw_handle& h) {
+  hipDeviceProp_t prop;
+  MCW_HIP(hipGetDeviceProperties(&prop, h.device));
+  const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+  TuneCache cache;
+  const int cand[3] = {1, 2, 4};
+  for (auto& L : h.levels) {
+    if (L.d.N() < (size_t)1 << 16) continue;
+    const std::string dims = std::to_string(L.d.NX()) + "x" + std::to_string(L.d.NY()) + "x" +
+                             std::to_string(L.d.NZ()) + (sizeof(T) == 4 ? "|f32" : "|f64");
+    int v = 0;
+    const bool have_gs = cache.get(arch + "|gs|" + dims, v);
+    if (have_gs) L.by_gs = v;
+    const bool have_res = cache.get(arch + "|res|" + dims, v);
+    if (have_res) L.by_res = v;
+    if (have_gs && have_res) continue;
+    launch_fill<T>(L.f.as<T>(), L.d.N(), T(0), h.stream);
+    launch_fill<T>(L.x.as<T>(), L.d.N(), T(0), h.stream);
+    const T* st = stencil_of<T>(L);
+    for (int which = 0; which < 2; ++which) {
+      if ((which == 0 && have_gs) || (which == 1 && have_res)) continue;
+      float best = 1e30f;
+      int best_by = 4;
+      for (int by : cand) {
+        auto run = [&] {
+          if (which == 0) launch_smooth_sweep<T>(L.d, h.faces, st, L.f.as<T>(), L.x.as<T>(), h.stream, by);
+          else
+            launch_residual<T>(L.d, h.faces, st, L.x.as<T>(), L.f.as<T>(), L.r.as<T>(), nullptr, nullptr,
+                               h.stream, by);
+        };
+        run();
+        MCW_HIP(hipEventRecord(h.ev[6], h.stream));
+        for (int r = 0; r < 3; ++r) run();
+        MCW_HIP(hipEventRecord(h.ev[7], h.stream));
+        MCW_HIP(hipEventSynchronize(h.ev[7]));
+        float ms = 0.f;
+        MCW_HIP(hipEventElapsedTime(&ms, h.ev[6], h.ev[7]));
+        if (ms < best) {
+          best = ms;
+          best_by = by;
+        }
+      }
+      if (which == 0) {
+        L.by_gs = best_by;
+        cache.put(arch + "|gs|" + dims, best_by);
+      } else {
+        L.by_res = best_by;
+        cache.put(arch + "|res|" + dims, best_by);
+      }
+      logf(h, "autotune %s %s: %d rows per block", which == 0 ? "gs" : "res", dims.c_str(), best_by);
+    }
+  }
+  cache.save();
 }
 
 // ---------------------------------------------------------------- set-up
@@ -628,15 +754,11 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
     Level& L = h.levels[l];
     const size_t n = L.d.N();
     const size_t es = f32 ? sizeof(float) : sizeof(double);
-    if (l > 0 || f32) {
-      L.x.alloc(n * es);
-      L.f.alloc(n * es);
-    }
-    if (l + 1 < h.levels.size()) L.r.alloc(n * es);
-    if (L.x.p) {
-      if (f32) launch_fill<float>(L.x.as<float>(), n, 0.f, h.stream);
-      else launch_fill<double>(L.x.as<double>(), n, 0.0, h.stream);
-    }
+    L.x.alloc(n * es);
+    L.f.alloc(n * es);
+    L.r.alloc(n * es);
+    if (f32) launch_fill<float>(L.x.as<float>(), n, 0.f, h.stream);
+    else launch_fill<double>(L.x.as<double>(), n, 0.0, h.stream);
   }
   h.f64.alloc(N * sizeof(double));
   h.r64.alloc(N * sizeof(double));
@@ -649,6 +771,10 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
   h.partials.alloc(h.n_partials * sizeof(double));
   h.scalars.alloc(8 * sizeof(double));
   MCW_HIP(hipHostMalloc((void**)&h.host_scalars, 8 * sizeof(double), hipHostMallocDefault));
+  if (opt.autotune) {
+    if (f32) autotune_levels<float>(h);
+    else autotune_levels<double>(h);
+  }
   MCW_HIP(hipStreamSynchronize(h.stream));
   if (opt.verbose) {
     for (size_t l = 0; l < h.levels.size(); ++l) {
@@ -700,6 +826,67 @@ Level& level_at(mcw_handle* h, int l, bool need_coarser) {
 
 bool is_f32(const mcw_handle* h) { return h->opt.precision == MCW_FP32_REFINE; }
 
+// Single-step entry points take natural-order vectors; the level buffers hold
+// the row-split copies the kernels work on.
+template <class T>
+void smooth_t(mcw_handle& h, int l, T* x, const T* f, int sweeps) {
+  Level& L = level_at(&h, l, false);
+  launch_relayout<T>(L.d, x, L.x.as<T>(), true, h.stream);
+  launch_relayout<T>(L.d, f, L.f.as<T>(), true, h.stream);
+  for (int s = 0; s < sweeps; ++s)
+    launch_smooth_sweep<T>(L.d, h.faces, stencil_of<T>(L), L.f.as<T>(), L.x.as<T>(), h.stream);
+  launch_relayout<T>(L.d, L.x.as<T>(), x, false, h.stream);
+}
+
+template <class T>
+void residual_t(mcw_handle& h, int l, const T* x, const T* f, T* r) {
+  Level& L = level_at(&h, l, false);
+  launch_relayout<T>(L.d, x, L.x.as<T>(), true, h.stream);
+  launch_relayout<T>(L.d, f, L.f.as<T>(), true, h.stream);
+  launch_residual<T>(L.d, h.faces, stencil_of<T>(L), L.x.as<T>(), L.f.as<T>(), L.r.as<T>(), nullptr,
+                     nullptr, h.stream);
+  launch_relayout<T>(L.d, L.r.as<T>(), r, false, h.stream);
+}
+
+template <class T>
+void restrict_t(mcw_handle& h, int l, const T* r, T* rc) {
+  Level& L = level_at(&h, l, true);
+  Level& C = h.levels[l + 1];
+  launch_relayout<T>(L.d, r, L.r.as<T>(), true, h.stream);
+  launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
+  launch_relayout<T>(C.d, C.f.as<T>(), rc, false, h.stream);
+}
+
+template <class T>
+void prolong_t(mcw_handle& h, int l, const T* e, T* x) {
+  Level& L = level_at(&h, l, true);
+  Level& C = h.levels[l + 1];
+  launch_relayout<T>(C.d, e, C.x.as<T>(), true, h.stream);
+  launch_relayout<T>(L.d, x, L.x.as<T>(), true, h.stream);
+  launch_prolong_dims<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, C.x.as<T>(), L.x.as<T>(), h.stream);
+  launch_relayout<T>(L.d, L.x.as<T>(), x, false, h.stream);
+}
+
+template <class T>
+void coarse_t(mcw_handle& h, const T* r, T* e) {
+  Level& L = h.levels.back();
+  launch_relayout<T>(L.d, r, L.f.as<T>(), true, h.stream);
+  launch_fill<T>(L.x.as<T>(), L.d.N(), T(0), h.stream);
+  launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(),
+                         L.f.as<T>(), L.x.as<T>(), h.stream);
+  launch_relayout<T>(L.d, L.x.as<T>(), e, false, h.stream);
+}
+
+template <class T>
+void vcycle_t(mcw_handle& h, T* x, const T* f) {
+  Level& L = h.levels[0];
+  launch_relayout<T>(L.d, x, L.x.as<T>(), true, h.stream);
+  launch_relayout<T>(L.d, f, L.f.as<T>(), true, h.stream);
+  vcycle<T>(h, 0, L.x.as<T>(), L.f.as<T>());
+  launch_relayout<T>(L.d, L.x.as<T>(), x, false, h.stream);
+}
+
+
 }  // namespace
 
 // ---------------------------------------------------------------- batched solves
@@ -727,6 +914,8 @@ class Batch {
     depth_ = 0;
     for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
     gs_.assign(depth_, {});
+    by_gs_.assign(depth_, 4);
+    by_res_.assign(depth_, 4);
     res_.assign(depth_, {});
     restr_.assign(depth_, {});
     fillx_.assign(depth_, {});
@@ -738,6 +927,16 @@ class Batch {
       std::vector<VecJob> fj;
       std::vector<CoarseJob> cj;
       std::vector<int> gsm[4], rm, rsm, pm, fm, cm;
+      // tile rows of this depth: the tuned shapes of its largest member
+      size_t big = 0;
+      for (int i = 0; i < m_; ++i) {
+        mcw_handle& h = *hs_[i];
+        if (d + 1 < (int)h.levels.size() && h.levels[d].d.N() > big) {
+          big = h.levels[d].d.N();
+          by_gs_[d] = h.levels[d].by_gs;
+          by_res_[d] = h.levels[d].by_res;
+        }
+      }
       for (int i = 0; i < m_; ++i) {
         mcw_handle& h = *hs_[i];
         const int L = (int)h.levels.size();
@@ -752,13 +951,13 @@ class Batch {
         }
         Level& C = h.levels[d + 1];
         for (int c = 0; c < 4; ++c) {
-          const ColJob J = col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, nullptr, c);
+          const ColJob J = col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, nullptr, c, by_gs_[d]);
           if (J.nblocks > 0) {
             gsj[c].push_back(J);
             gsm[c].push_back(i);
           }
         }
-        rj.push_back(col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, V.r.p, -1));
+        rj.push_back(col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
         rm.push_back(i);
         rsj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, V.r.p, C.f.p, true));
         rsm.push_back(i);
@@ -802,8 +1001,10 @@ class Batch {
       div.push_back(A);
       rec.push_back(recover_job(h, nullptr, nullptr, nullptr));
       sc.push_back(vec_job(h.levels[0].f.p, h.r64.p, N, nullptr));
+      sc.back().NX = h.d.NX();
       f0.push_back(vec_job(h.levels[0].x.p, nullptr, N, nullptr));
       up.push_back(vec_job(nullptr, h.levels[0].x.p, N, nullptr));
+      up.back().NX = h.d.NX();
       s1.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 1, nullptr});
       s2.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 2, nullptr});
     }
@@ -1076,14 +1277,14 @@ class Batch {
     launch_coarse_batched<float>(fix(coarse_[d]), std::max(max_coarse_, 1), s_);
     if (res_[d].njobs == 0) return;
     for (int s = 0; s < nu_pre; ++s)
-      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_);
-    launch_residual_batched<float>(fix(res_[d]), s_);
+      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d]);
+    launch_residual_batched<float>(fix(res_[d]), s_, by_res_[d]);
     launch_restrict_batched<float>(fix(restr_[d]), s_);
     launch_fill_batched<float>(fix(fillx_[d]), s_);
     if (d + 1 < depth_) vcycle_levels(d + 1);
     launch_prolong_batched<float>(fix(prol_[d]), s_);
     for (int s = 0; s < nu_post; ++s)
-      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_);
+      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d]);
   }
 
   void vcycle() {
@@ -1114,6 +1315,7 @@ class Batch {
   hipStream_t s_;
   int depth_ = 0, max_coarse_ = 0;
   std::vector<std::array<WorkList, 4>> gs_;
+  std::vector<int> by_gs_, by_res_;
   std::vector<WorkList> res_, restr_, fillx_, prol_, coarse_;
   WorkList zf_{}, rhs_{}, res64_{}, div_{}, rec_{}, sc_{}, f0_{}, up_{};
   std::vector<VecJob> zf_jobs_, sc_jobs_, f0_jobs_, up_jobs_;
@@ -1174,6 +1376,7 @@ void mcw_default_options(mcw_options* o) {
   o->coarse_direct_max = 1024;
   o->use_graph = 1;
   o->verbose = std::getenv("MCW_LOG") ? 1 : 0;
+  o->autotune = 1;
 }
 
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
@@ -1306,6 +1509,17 @@ mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda,
   });
 }
 
+mcw_status mcw_tile_shape(const mcw_handle* hc, int32_t l, int32_t* rows_smooth, int32_t* rows_residual) {
+  auto* h = const_cast<mcw_handle*>(hc);
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    const Level& L = level_at(h, l, false);
+    if (rows_smooth) *rows_smooth = L.by_gs;
+    if (rows_residual) *rows_residual = L.by_res;
+    return MCW_OK;
+  });
+}
+
 int32_t mcw_num_levels(const mcw_handle* h) { return h ? (int32_t)h->levels.size() : 0; }
 
 mcw_status mcw_level_info(const mcw_handle* hc, int32_t l, int32_t dims[3], int32_t* coarsen_h,
@@ -1360,15 +1574,8 @@ mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t 
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!x || !f || sweeps < 0) Fail::arg("bad smoother arguments");
-    Level& L = level_at(h, l, false);
-    for (int s = 0; s < sweeps; ++s) {
-      if (is_f32(h))
-        launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), static_cast<const float*>(f),
-                                   static_cast<float*>(x), h->stream);
-      else
-        launch_smooth_sweep<double>(L.d, h->faces, L.st64.as<double>(), static_cast<const double*>(f),
-                                    static_cast<double*>(x), h->stream);
-    }
+    if (is_f32(h)) smooth_t(*h, l, static_cast<float*>(x), static_cast<const float*>(f), sweeps);
+    else smooth_t(*h, l, static_cast<double*>(x), static_cast<const double*>(f), sweeps);
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
@@ -1378,15 +1585,11 @@ mcw_status mcw_residual(mcw_handle* h, int32_t l, const void* x, const void* f, 
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!x || !f || !r) Fail::arg("null vector");
-    Level& L = level_at(h, l, false);
     if (is_f32(h))
-      launch_residual<float>(L.d, h->faces, L.st32.as<float>(), static_cast<const float*>(x),
-                             static_cast<const float*>(f), static_cast<float*>(r), nullptr, nullptr,
-                             h->stream);
+      residual_t(*h, l, static_cast<const float*>(x), static_cast<const float*>(f), static_cast<float*>(r));
     else
-      launch_residual<double>(L.d, h->faces, L.st64.as<double>(), static_cast<const double*>(x),
-                              static_cast<const double*>(f), static_cast<double*>(r), nullptr,
-                              nullptr, h->stream);
+      residual_t(*h, l, static_cast<const double*>(x), static_cast<const double*>(f),
+                 static_cast<double*>(r));
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
@@ -1396,14 +1599,8 @@ mcw_status mcw_restrict(mcw_handle* h, int32_t l, const void* r, void* rc) {
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!r || !rc) Fail::arg("null vector");
-    Level& L = level_at(h, l, true);
-    const Level& C = h->levels[l + 1];
-    if (is_f32(h))
-      launch_restrict<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, static_cast<const float*>(r),
-                             static_cast<float*>(rc), h->stream);
-    else
-      launch_restrict<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
-                              static_cast<const double*>(r), static_cast<double*>(rc), h->stream);
+    if (is_f32(h)) restrict_t(*h, l, static_cast<const float*>(r), static_cast<float*>(rc));
+    else restrict_t(*h, l, static_cast<const double*>(r), static_cast<double*>(rc));
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
@@ -1413,14 +1610,8 @@ mcw_status mcw_prolong(mcw_handle* h, int32_t l, const void* e, void* x) {
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!e || !x) Fail::arg("null vector");
-    Level& L = level_at(h, l, true);
-    const Level& C = h->levels[l + 1];
-    if (is_f32(h))
-      launch_prolong_dims<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
-                                 static_cast<const float*>(e), static_cast<float*>(x), h->stream);
-    else
-      launch_prolong_dims<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz,
-                                  static_cast<const double*>(e), static_cast<double*>(x), h->stream);
+    if (is_f32(h)) prolong_t(*h, l, static_cast<const float*>(e), static_cast<float*>(x));
+    else prolong_t(*h, l, static_cast<const double*>(e), static_cast<double*>(x));
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
@@ -1430,12 +1621,8 @@ mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e) {
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!r || !e) Fail::arg("null vector");
-    if (is_f32(h))
-      launch_coarse_solve<float>(h->n_coarse, h->coarse_inv.as<double>(), h->coarse_idx.as<int>(),
-                                 static_cast<const float*>(r), static_cast<float*>(e), h->stream);
-    else
-      launch_coarse_solve<double>(h->n_coarse, h->coarse_inv.as<double>(), h->coarse_idx.as<int>(),
-                                  static_cast<const double*>(r), static_cast<double*>(e), h->stream);
+    if (is_f32(h)) coarse_t(*h, static_cast<const float*>(r), static_cast<float*>(e));
+    else coarse_t(*h, static_cast<const double*>(r), static_cast<double*>(e));
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
@@ -1445,10 +1632,57 @@ mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f) {
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
     if (!x || !f) Fail::arg("null vector");
-    if (is_f32(h))
-      vcycle<float>(*h, 0, static_cast<float*>(x), static_cast<const float*>(f));
-    else
-      vcycle<double>(*h, 0, static_cast<double*>(x), static_cast<const double*>(f));
+    if (is_f32(h)) vcycle_t(*h, static_cast<float*>(x), static_cast<const float*>(f));
+    else vcycle_t(*h, static_cast<double*>(x), static_cast<const double*>(f));
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (kernel < 0 || kernel > 4 || reps < 0) Fail::arg("bad kernel or repetition count");
+    Level& L = level_at(h, l, kernel == 2 || kernel == 3);
+    if (kernel == 4 && l != 0) Fail::arg("the matrix-free residual runs on level 0");
+    for (int r = 0; r < reps; ++r) {
+      if (kernel == 4) {
+        launch_apply(*h, h->t64.as<double>(), h->f64.as<double>(), h->r64.as<double>(), 1, nullptr,
+                     nullptr);
+        continue;
+      }
+      if (is_f32(h)) {
+        float *x = L.x.as<float>(), *f = L.f.as<float>(), *rr = L.r.as<float>();
+        if (kernel == 0)
+          launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), f, x, h->stream, L.by_gs);
+        if (kernel == 1)
+          launch_residual<float>(L.d, h->faces, L.st32.as<float>(), x, f, rr, nullptr, nullptr, h->stream,
+                                 L.by_res);
+        if (kernel == 2 || kernel == 3) {
+          Level& C = h->levels[l + 1];
+          if (kernel == 2)
+            launch_restrict<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, rr, C.f.as<float>(), h->stream);
+          else
+            launch_prolong_dims<float>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, C.x.as<float>(), x,
+                                       h->stream);
+        }
+      } else {
+        double *x = L.x.as<double>(), *f = L.f.as<double>(), *rr = L.r.as<double>();
+        if (kernel == 0)
+          launch_smooth_sweep<double>(L.d, h->faces, L.st64.as<double>(), f, x, h->stream, L.by_gs);
+        if (kernel == 1)
+          launch_residual<double>(L.d, h->faces, L.st64.as<double>(), x, f, rr, nullptr, nullptr, h->stream,
+                                  L.by_res);
+        if (kernel == 2 || kernel == 3) {
+          Level& C = h->levels[l + 1];
+          if (kernel == 2)
+            launch_restrict<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, rr, C.f.as<double>(), h->stream);
+          else
+            launch_prolong_dims<double>(L.d, C.d, h->faces, L.dmx, L.dmy, L.dmz, C.x.as<double>(), x,
+                                        h->stream);
+        }
+      }
+    }
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });

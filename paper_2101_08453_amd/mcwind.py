@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("nu_pre", ctypes.c_int32),
                 ("nu_post", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("coarsen_rule", ctypes.c_int32), ("coarse_direct_max", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -106,6 +107,8 @@ SIGNATURES = {
     "mcw_prolong": (I32, [H, I32, P, P]),
     "mcw_coarse_solve": (I32, [H, P, P]),
     "mcw_vcycle": (I32, [H, P, P]),
+    "mcw_run_kernel": (I32, [H, I32, I32, I32]),
+    "mcw_tile_shape": (I32, [H, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "mcw_status_string": (ctypes.c_char_p, [I32]),
     "mcw_last_error": (ctypes.c_char_p, [H]),
 }
@@ -152,7 +155,7 @@ class Grid:
 
     def __init__(self, X, Y, Z, a, gamma=GAMMA_BOTTOM, precision="fp32_refine", rtol=1e-8,
                  max_cycles=200, nu_pre=2, nu_post=2, inner_cycles=0, coarsen_rule="operator",
-                 coarse_direct_max=1024, use_graph=True, verbose=False):
+                 coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True):
         L = lib()
         self._h = H()
         nzp, nyp, nxp = X.shape
@@ -178,6 +181,7 @@ class Grid:
         o.coarsen_rule = RULES[coarsen_rule]
         o.coarse_direct_max = coarse_direct_max
         o.use_graph = 1 if use_graph else 0
+        o.autotune = 1 if autotune else 0
         o.verbose = 1 if (verbose or os.environ.get("MCW_LOG")) else 0
         self.precision = precision
         self.vdtype = torch.float32 if precision == "fp32_refine" else torch.float64
@@ -299,6 +303,12 @@ class Grid:
     def levels(self):
         return [self.level(l) for l in range(self.num_levels())]
 
+    def tile_rows(self, l):
+        """Tile rows per block the autotuner chose for level l: (colour pass, residual)."""
+        gs, res = I32(), I32()
+        self._check(lib().mcw_tile_shape(self._h, l, ctypes.byref(gs), ctypes.byref(res)))
+        return gs.value, res.value
+
     def stencil(self, l, precision=None):
         """(27, NZ, NY, NX) coefficients of level l in natural node order."""
         precision = precision or self.precision
@@ -338,6 +348,12 @@ class Grid:
         self._check(lib().mcw_coarse_solve(self._h, _ptr(r, self.vdtype, self.level_shape(L), "r"),
                                            _ptr(e, self.vdtype, self.level_shape(L), "e")))
         return e
+
+    KERNELS = {"smooth": 0, "residual": 1, "restrict": 2, "prolong": 3, "residual64": 4}
+
+    def run_kernel(self, l, kernel, reps=1):
+        """Launch one multigrid kernel `reps` times on level l's own buffers (timing)."""
+        self._check(lib().mcw_run_kernel(self._h, l, self.KERNELS[kernel], reps))
 
     def vcycle(self, x, f):
         s = self.level_shape(0)

@@ -199,3 +199,22 @@ def test_c2_size_solve_sampled_against_oracle(precision):
     Xw, Yw, Zw = (A[:, 100:131, 120:151] for A in (p.X, p.Y, p.Z))
     u_ref = fem.recover(Xw, Yw, Zw, p.u0[:, :, 100:130, 120:150], p.a, lw)
     assert gc.rel_err(u_h[:, :, 100:130, 120:150], u_ref) < 1e-12
+
+
+def test_autotuned_tile_shapes_are_cached_and_do_not_change_results(tmp_path, monkeypatch):
+    mcwind = _mcw()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
+    p = inputs.hills_problem(160, 120, 8, 4, 5, a=(1.0, 1.0, 2.0))
+    g1, u0 = mcwind.grid_from_problem(p, autotune=True)
+    g2, _ = mcwind.grid_from_problem(p, autotune=False)
+    shapes = [g1.tile_rows(l) for l in range(g1.num_levels())]
+    assert all(s in (1, 2, 4) for pair in shapes for s in pair)
+    assert g2.tile_rows(0) == (4, 4)
+    text = cache.read_text()
+    assert "|gs|161x121x9|f32" in text and "|res|161x121x9|f32" in text
+    g3, _ = mcwind.grid_from_problem(p, autotune=True)
+    assert [g3.tile_rows(l) for l in range(g3.num_levels())] == shapes
+    a, ua, _ = g1.solve(u0)
+    b, ub, _ = g2.solve(u0)
+    assert torch.equal(a, b) and torch.equal(ua, ub)
