@@ -48,8 +48,11 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip per-kernel timing")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
-                    help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch")
+    ap.add_argument("--no-krylov", action="store_true",
+                    help="skip the multigrid-preconditioned CG comparison")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules"],
+                    help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
+                         "rules: coarsening rules across penalties and layer stretching")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -228,6 +231,45 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_rules(args):
+    """Base method (full 2x2x2 coarsening) against adaptive semicoarsening (the
+    operator-consistent and the printed ratio) on 512x512x15 fractal terrain
+    with the slopes of the 3000x3000 grid, for a3 in {1, 2, 5, 10} and layer
+    stretching 1.0 / 1.2: V-cycles and rate to 1e-8 (plain FP64, cold start),
+    by the multigrid iteration and by multigrid-preconditioned CG."""
+    import torch
+
+    from paper_2101_08453_amd import inputs, mcwind
+    n, nz = 512, 15
+    rows = []
+    for ratio in (1.0, 1.2):
+        for a3 in (1.0, 2.0, 5.0, 10.0):
+            rng = np.random.default_rng(3)
+            zs = inputs.fractal_terrain(n, n, 800.0 * n / 3000.0, rng)
+            zeta = inputs.vertical_levels(nz, first=5.0 if ratio > 1.0 else 20.0, ratio=ratio)
+            X, Y, Z = inputs.terrain_grid(zs, zeta, 30.0, 30.0)
+            u0 = inputs._log_wind(n, n, nz, zeta, 8.0, 0.3)
+            p = inputs.Problem("rules", X, Y, Z, u0, np.array([1.0, 1.0, a3]))
+            for rule in ("operator", "literal", "full"):
+                for krylov in (False, True):
+                    g, u0t = mcwind.grid_from_problem(p, precision="fp64", coarsen_rule=rule,
+                                                      max_cycles=400, krylov=krylov)
+                    g.solve(u0t, check=False, want_u=False)  # warm-up (graph capture)
+                    lam, _, info = g.solve(u0t, check=False)
+                    lv = [L["dims"] for L in g.levels()]
+                    work = sum((d[0] + 1) * (d[1] + 1) * (d[2] + 1) for d in lv) / p.n_nodes
+                    rows.append({"stretch": ratio, "a3": a3, "rule": rule,
+                                 "method": "mg-pcg" if krylov else "multigrid",
+                                 "cycles": info["cycles"], "rho": round(info["rho"], 3),
+                                 "status": info["status"], "levels": len(lv),
+                                 "grid_work": round(work, 3), "ms": round(info["ms_total"], 1)})
+                    log(rows[-1])
+                    g.close()
+                    del u0t
+                    torch.cuda.empty_cache()
+    print(json.dumps({"workload": "coarsening rules, 512x512x15", "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -247,6 +289,9 @@ def main():
         del a, b
     if args.workload == "c4":
         bench_c4(args)
+        return
+    if args.workload == "rules":
+        bench_rules(args)
         return
 
     from paper_2101_08453_amd import inputs, mcwind
@@ -308,10 +353,39 @@ def main():
             kernels = kernel_table(g, stream, n_free)
             for k, v in kernels.items():
                 log(f"kernel {k}: {v['ms']:.3f} ms, {v['GB/s']:.0f} GB/s")
+        del g
+        torch.cuda.empty_cache()
+        krylov = None
+        if not args.no_krylov:
+            # the same solve by CG preconditioned with one symmetric V-cycle per step
+            t0 = time.perf_counter()
+            gk = mcwind.Grid(X, Y, Z, p.a, precision="fp32_refine", rtol=1e-8, krylov=True)
+            sk = time.perf_counter() - t0
+            lamk = torch.empty_like(lam_prev)
+            lamk.copy_(lam_prev)
+            gk.solve(u0p, lam=lamk, want_u=False)  # warm-up (captures the CG step graph)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = max(1, min(args.steps, 3))
+            e0.record(stream)
+            for _ in range(reps):
+                lamk.copy_(lam_prev)
+                _, _, ik = gk.solve(u0p, lam=lamk)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            msk = e0.elapsed_time(e1) / reps
+            diff = float((lamk - lam).abs().max() / lam.abs().max())
+            krylov = {"value": round(N / msk / 1e3, 2), "ms_per_step": round(msk, 3),
+                      "cycles": ik["cycles"], "refinements": ik["outer_steps"],
+                      "rel_residual": ik["rel_residual"], "rel_divergence": ik["rel_divergence"],
+                      "rho": ik["rho"], "setup_s": round(sk, 2),
+                      "lambda_rel_diff_vs_multigrid": diff}
+            log(f"mg-pcg: {msk:.1f} ms/step, {ik['cycles']} cycles, {ik['outer_steps']} refinements, "
+                f"rel res {ik['rel_residual']:.2e}, lambda diff {diff:.2e}")
+            del gk
+            torch.cuda.empty_cache()
         fp64 = None
         if not args.no_fp64:
-            del g
-            torch.cuda.empty_cache()
             t0 = time.perf_counter()
             g64 = mcwind.Grid(X, Y, Z, p.a, precision="fp64", rtol=1e-8)
             s64 = time.perf_counter() - t0
@@ -365,6 +439,7 @@ def main():
                   "ms_finish": info["ms_finish"], "levels": info["levels"]},
         "roofline": roof,
         "kernels": kernels,
+        "mg_pcg": krylov,
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }

@@ -107,6 +107,11 @@ typedef struct {
   int32_t autotune;           /* time tile shapes of the colour pass and residual per level at
                                  set-up and keep the fastest (cached in the JSON file named by
                                  MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); default 1 */
+  int32_t krylov;             /* 0: the multigrid iteration of Sec. 3 (default); 1: conjugate
+                                 gradients preconditioned by one symmetric V-cycle (the
+                                 post-smoothing sweeps run in reverse: colours 3..0, each
+                                 column top-down), restarted at every refinement step;
+                                 needs nu_pre == nu_post */
 } mcw_options;
 
 #define MCW_MAX_LEVELS 24
@@ -114,7 +119,7 @@ typedef struct {
 
 typedef struct {
   int32_t outer_steps;            /* FP64 residual evaluations after the start */
-  int32_t cycles;                 /* V-cycles performed */
+  int32_t cycles;                 /* V-cycles performed (with krylov = 1: CG steps, one V-cycle each) */
   double rel_residual;            /* final ||f - K lambda|| / ||f|| (FP64, free nodes) */
   double rel_divergence;          /* ||D|| / ||D0||, D the weak divergence of u0 + A^-1 grad lambda */
   double rho;                     /* mean residual reduction per V-cycle */
@@ -216,9 +221,12 @@ mcw_status mcw_level_info(const mcw_handle* h, int32_t l, int32_t dims[3], int32
  * FP32 copy used by the V-cycles (out is then float*). */
 mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out);
 
-/* One or more Gauss-Seidel sweeps (4 colour passes, columns bottom-up) on
- * level l in the handle's precision of the V-cycle (double* for MCW_FP64
- * handles, float* for MCW_FP32_REFINE): x in/out, f in, level-sized node vectors. */
+/* |sweeps| Gauss-Seidel sweeps on level l in the handle's precision of the
+ * V-cycle (double* for MCW_FP64 handles, float* for MCW_FP32_REFINE): x in/out,
+ * f in, level-sized node vectors.  sweeps > 0: the smoother of Sec. 3 (colours
+ * (0,0),(1,0),(0,1),(1,1), each column bottom-up); sweeps < 0: the reverse
+ * (adjoint) sweep, colours (1,1),(0,1),(1,0),(0,0), each column top-down.
+ * |sweeps| <= 1000. */
 mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t sweeps);
 
 /* r = f - K_l x at free nodes, 0 at fixed nodes (V-cycle precision). */

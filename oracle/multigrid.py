@@ -25,6 +25,9 @@ CPU-baseline leg; never by the product path.
   is the base method: coarsen every direction.  Stop when the free unknowns
   fit the direct solver, or nothing coarsens; if nothing coarsens while the
   grid is still too large, coarsen horizontally anyway.
+* Beyond the paper: the symmetric V-cycle (post-smoothing in the reverse
+  order) and conjugate gradients preconditioned by it, the textbook method
+  (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1).
 """
 from __future__ import annotations
 
@@ -180,16 +183,21 @@ def colour_order(nx, ny, nz, mask):
     return np.asarray(order, dtype=np.int64)
 
 
-def gs_sweep_full(K_full, mask, dims, x, f, order=None):
+def gs_sweep_full(K_full, mask, dims, x, f, order=None, reverse=False):
     """One Gauss-Seidel sweep on full-length vectors x, f (fixed nodes untouched).
 
     Updating the nodes one by one in `order` is the same as solving with the
     lower triangle (diagonal included) of K permuted to that order:
     x_pi += tril(K_pi)^{-1} (f - K x)_pi.
+    reverse=True visits the nodes in the opposite order (colours (1,1),(0,1),
+    (1,0),(0,0), each column top to bottom): the adjoint sweep, which makes a
+    V-cycle symmetric when it follows the forward pre-smoothing.
     """
     nx, ny, nz = dims
     if order is None:
         order = colour_order(nx, ny, nz, mask)
+    if reverse:
+        order = order[::-1]
     x = np.array(x, dtype=np.float64)
     Kp = K_full[order][:, order].tocsr()
     r = f[order] - (K_full @ x)[order]
@@ -198,28 +206,36 @@ def gs_sweep_full(K_full, mask, dims, x, f, order=None):
 
 
 class Multigrid:
-    """V-cycle on the free-node systems of a hierarchy (eqs. (6)-(7))."""
+    """V-cycle on the free-node systems of a hierarchy (eqs. (6)-(7)).
 
-    def __init__(self, levels, nu_pre=2, nu_post=2):
+    symmetric=True runs the post-smoothing sweeps in the reverse order (not in
+    the paper): with nu_pre == nu_post the V-cycle from zero is then a
+    symmetric positive definite operator B, usable as a CG preconditioner."""
+
+    def __init__(self, levels, nu_pre=2, nu_post=2, symmetric=False):
         self.levels = levels
         self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.symmetric = symmetric
         self._orders = []
         self._tri = []
+        self._tri_rev = []
         for L in levels:
             order_full = colour_order(L.nx, L.ny, L.nz, L.mask)
             pos = np.full(L.mask.size, -1, dtype=np.int64)
             pos[L.free] = np.arange(L.free.size)
             order = pos[order_full]  # positions within the free-node vector
-            Kp = L.K[order][:, order].tocsr()
             self._orders.append(order)
-            self._tri.append(sp.tril(Kp).tocsr())
+            self._tri.append(sp.tril(L.K[order][:, order]).tocsr())
+            rev = order[::-1]
+            self._tri_rev.append(sp.tril(L.K[rev][:, rev]).tocsr())
         self._coarse = np.linalg.cholesky(levels[-1].K.toarray())
 
-    def smooth(self, l, x, f):
-        order = self._orders[l]
+    def smooth(self, l, x, f, reverse=False):
+        order = self._orders[l][::-1] if reverse else self._orders[l]
+        tri = self._tri_rev[l] if reverse else self._tri[l]
         r = f - self.levels[l].K @ x
         x = x.copy()
-        x[order] += spla.spsolve_triangular(self._tri[l], r[order], lower=True)
+        x[order] += spla.spsolve_triangular(tri, r[order], lower=True)
         return x
 
     def coarse_solve(self, f):
@@ -236,8 +252,39 @@ class Multigrid:
         rc = L.P.T @ (f - L.K @ x)
         x = x + L.P @ self.vcycle(np.zeros(rc.shape), rc, l + 1)
         for _ in range(self.nu_post):
-            x = self.smooth(l, x, f)
+            x = self.smooth(l, x, f, reverse=self.symmetric)
         return x
+
+    def precondition(self, r):
+        """B r: one V-cycle on K z = r from z = 0."""
+        return self.vcycle(np.zeros_like(r), r)
+
+    def pcg(self, f, steps=None, rtol=1e-12, maxiter=500):
+        """Conjugate gradients on K x = f from x = 0, preconditioned by one
+        V-cycle per step (Hestenes-Stiefel recurrences, Fletcher-Reeves beta).
+        Runs `steps` steps if given, else until ||f - K x|| <= rtol ||f||.
+        Returns x and the relative residual norms of the recurrence."""
+        K = self.levels[0].K
+        x = np.zeros_like(f)
+        r = f.copy()
+        nf = np.linalg.norm(f)
+        z = self.precondition(r)
+        p = z.copy()
+        rz = r @ z
+        hist = []
+        for it in range(steps if steps is not None else maxiter):
+            q = K @ p
+            alpha = rz / (p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            hist.append(np.linalg.norm(r) / nf)
+            if steps is None and hist[-1] <= rtol:
+                break
+            z = self.precondition(r)
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        return x, hist
 
     def convergence_factor(self, cycles=12, seed=0, skip=4):
         """Asymptotic residual reduction per V-cycle for K e = 0 from a random start."""

@@ -740,6 +740,7 @@ void launch_apply(const mcw_handle& h, const double* x, const double* f, double*
   A.out = out;
   A.partials = partials;
   const dim3 g = tile_grid(h);
+  if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
   if (mode == 0)
     elem_tile_kernel<M_APPLY><<<g, 256, 0, h.stream>>>(A);
   else
@@ -754,6 +755,7 @@ void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partia
   A.out = f;
   A.partials = partials;
   const dim3 g = tile_grid(h);
+  if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
   elem_tile_kernel<M_RHS><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
@@ -767,6 +769,7 @@ void launch_divergence(const mcw_handle& h, const double* u0, const double* lam,
   A.out = D;
   A.partials = partials;
   const dim3 g = tile_grid(h);
+  if (partials) need_partials(2 * (size_t)g.x * g.y, h.n_partials);
   elem_tile_kernel<M_DIV><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
@@ -779,6 +782,7 @@ void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_la
   A.out = g_lam;
   A.partials = partials;
   const dim3 g = tile_grid(h);
+  if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
   elem_tile_kernel<M_ADJ><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
@@ -793,6 +797,7 @@ void launch_recover(const mcw_handle& h, const double* u0, const double* lam, do
 void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const double* lam,
                              const double* mu, float* dL_du0, double* partials, size_t* n_part) {
   const dim3 g((h.d.nx + 63) / 64, (h.d.ny + 3) / 4);
+  need_partials(3 * (size_t)g.x * g.y, h.n_partials);
   adjoint_elem_kernel<<<g, 256, 0, h.stream>>>(h.X.as<double>(), h.Y.as<double>(),
                                                h.Z.as<double>(), lam, mu, g_u, dL_du0, partials,
                                                h.d.nx, h.d.ny, h.d.nz);
@@ -803,6 +808,7 @@ void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const doubl
 void launch_check_finite(const mcw_handle& h, const double* v, size_t n, double* partials,
                          size_t* n_part) {
   const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  need_partials(blocks, h.n_partials);
   sumsq_kernel<<<blocks, 256, 0, h.stream>>>(v, n, partials);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = blocks;

@@ -29,6 +29,14 @@ struct Error {
 
 #define MCW_CHECK_LAUNCH() MCW_HIP(hipGetLastError())
 
+// Every launch that writes per-block partial sums checks, before it launches,
+// that its blocks times channels fit the buffer.
+inline void need_partials(size_t entries, size_t cap) {
+  if (entries > cap)
+    throw Error{MCW_HIP_ERROR, "internal error: " + std::to_string(entries) +
+                                   " partial sums exceed the buffer of " + std::to_string(cap)};
+}
+
 // ---------------------------------------------------------------- device buffers
 
 struct DevBuf {
@@ -269,6 +277,11 @@ struct mcw_handle {
   // hipGraph of one FP32 V-cycle (level vectors are fixed per handle)
   hipGraphExec_t vgraph = nullptr;
   bool vgraph_ready = false;
+  // conjugate gradients (krylov = 1): level-0 vectors in the row-split order;
+  // FP32 refinement keeps r and z in the level-0 f and x
+  mcw::DevBuf kr, kz, kp, kq, ke;
+  hipGraphExec_t kgraph = nullptr;  // one CG step
+  bool kgraph_ready = false;
   std::string last_error;
 };
 
@@ -302,10 +315,26 @@ void launch_recover_batched(const WorkList& W, hipStream_t s);
 // Multigrid kernels (templated on the V-cycle precision)
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s, int by = 4);
+                         hipStream_t s, int by = 4, bool reverse = false);
+// preconditioned conjugate gradients; sc = device scalars {r.z, alpha, beta, r.r}
+void launch_cg_reset(double* sc, hipStream_t s);
+template <class T>
+void launch_cg_beta(const T* z, const T* r, const T* q, size_t n, double* partials, size_t cap,
+                    double* sc, hipStream_t s);
+void launch_cg_alpha(size_t n_part, const double* partials, double* sc, hipStream_t s);
+template <class T>
+void launch_add(T* y, const T* x, size_t n, hipStream_t s);
+template <class T>
+void launch_cg_direction(T* p, const T* z, const double* sc, size_t n, hipStream_t s);
+template <class T>
+void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, double* partials,
+                      size_t cap, hipStream_t s);
+template <class T>
+void launch_neg_apply_dot(const Dims& d, const Faces& fc, const T* st, const T* p, T* q,
+                          double* partials, size_t cap, size_t* n_part, hipStream_t s, int by);
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s, int by = 4);
+                     double* partials, size_t* n_part, hipStream_t s, int by = 4, size_t cap = 0);
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                      const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s);

@@ -100,7 +100,7 @@ __device__ __forceinline__ void block_sum_to(double v, double* s_red, double* ou
 // pointwise Gauss-Seidel from the bottom to the top.  Neighbour columns belong
 // to other colours and are not changed during the pass; the value below is
 // this thread's own freshly updated one.
-template <class T>
+template <class T, bool REV = false>
 __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
   const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ f = static_cast<const T*>(J.f);
@@ -121,53 +121,93 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
   const size_t plane = (size_t)NX * NY;
   const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
   T xm[9], x0[9], xp[9];
-  {
-    const size_t pm = (size_t)(kf > 0 ? kf - 1 : 0) * plane, p0 = (size_t)kf * plane;
+  if (!REV) {
+    // bottom to top: the value below is this thread's fresh one
+    {
+      const size_t pm = (size_t)(kf > 0 ? kf - 1 : 0) * plane, p0 = (size_t)kf * plane;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      xm[q] = x[pm + cols[q]];
-      x0[q] = x[p0 + cols[q]];
+      for (int q = 0; q < 9; ++q) {
+        xm[q] = x[pm + cols[q]];
+        x0[q] = x[p0 + cols[q]];
+      }
     }
-  }
-  for (int k = kf; k <= kl; ++k) {
-    const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
+    for (int k = kf; k <= kl; ++k) {
+      const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
-    T a[SW];
-    load_stencil(st, L.node(i, j, k), a);
-    T s = f[(size_t)k * plane + cols[4]];
+      for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
+      T a[SW];
+      load_stencil(st, L.node(i, j, k), a);
+      T s = f[(size_t)k * plane + cols[4]];
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-      if (o == 13) continue;
-      const int dk = o / 9, q = o % 9;
-      const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
-      s -= a[o] * xv;
+      for (int o = 0; o < 27; ++o) {
+        if (o == 13) continue;
+        const int dk = o / 9, q = o % 9;
+        const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
+        s -= a[o] * xv;
+      }
+      const T xn = s / a[13];
+      x[(size_t)k * plane + cols[4]] = xn;
+      x0[4] = xn;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        xm[q] = x0[q];
+        x0[q] = xp[q];
+      }
     }
-    const T xn = s / a[13];
-    x[(size_t)k * plane + cols[4]] = xn;
-    x0[4] = xn;
+  } else {
+    // top to bottom (the adjoint sweep of a symmetric V-cycle)
+    {
+      const size_t pp = (size_t)(kl + 1 < NZ ? kl + 1 : NZ - 1) * plane, p0 = (size_t)kl * plane;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      xm[q] = x0[q];
-      x0[q] = xp[q];
+      for (int q = 0; q < 9; ++q) {
+        xp[q] = x[pp + cols[q]];
+        x0[q] = x[p0 + cols[q]];
+      }
+    }
+    for (int k = kl; k >= kf; --k) {
+      const size_t pm = (size_t)(k > 0 ? k - 1 : 0) * plane;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) xm[q] = x[pm + cols[q]];
+      T a[SW];
+      load_stencil(st, L.node(i, j, k), a);
+      T s = f[(size_t)k * plane + cols[4]];
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        if (o == 13) continue;
+        const int dk = o / 9, q = o % 9;
+        const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
+        s -= a[o] * xv;
+      }
+      const T xn = s / a[13];
+      x[(size_t)k * plane + cols[4]] = xn;
+      x0[4] = xn;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        xp[q] = x0[q];
+        x0[q] = xm[q];
+      }
     }
   }
 }
 
-template <class T>
+template <class T, bool REV>
 __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
-  gs_pass_body<T>(J, xcd_remap(blockIdx.x, J.nblocks));
+  gs_pass_body<T, REV>(J, xcd_remap(blockIdx.x, J.nblocks));
 }
+
+template <class T>
+__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false>(J, b); }
 
 template <class T>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, gs_pass_body<T>)
+  MCW_BATCHED_LOOP(ColJob, gs_pass_fwd<T>)
 }
 
 // ---------------------------------------------------------------- residual
 
-// r = f - K x at free nodes, 0 at fixed nodes; returns this thread's sum of r^2.
-template <class T>
+// r = f - K x at free nodes (f null: r = -K x), 0 at fixed nodes; returns this
+// thread's sum of r^2, or of x r with DOTX.
+template <class T, bool DOTX = false>
 __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ x = static_cast<const T*>(J.x);
@@ -208,7 +248,7 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
     for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
     T a[SW];
     load_stencil(st, L.node(i, j, k), a);
-    T s = f[(size_t)k * plane + own];
+    T s = f ? f[(size_t)k * plane + own] : T(0);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       const int dk = o / 9, q = o % 9;
@@ -217,7 +257,7 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
     }
     const T res = (k >= kf && k <= kl) ? s : T(0);
     r[(size_t)k * plane + own] = res;
-    acc += (double)res * (double)res;
+    acc += (double)(DOTX ? x0[4] : res) * (double)res;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       xm[q] = x0[q];
@@ -227,10 +267,10 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   return acc;
 }
 
-template <class T, bool NORM>
+template <class T, bool NORM, bool DOTX = false>
 __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restrict__ partials) {
   __shared__ double s_red[256];
-  const double acc = residual_body<T>(J, xcd_remap(blockIdx.x, J.nblocks));
+  const double acc = residual_body<T, DOTX>(J, xcd_remap(blockIdx.x, J.nblocks));
   if (NORM) {
     // blocks narrower than 256 threads: the missing lanes add zero
     if (threadIdx.x == 0)
@@ -636,25 +676,175 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s, int by) {
-  for (int c = 0; c < 4; ++c) {
+                         hipStream_t s, int by, bool reverse) {
+  for (int cc = 0; cc < 4; ++cc) {
+    const int c = reverse ? 3 - cc : cc;
     const ColJob J = col_job(d, fc, st, f, x, nullptr, c, by);
     if (J.nblocks <= 0) continue;
-    gs_pass_kernel<T><<<J.nblocks, BX * by, 0, s>>>(J);
+    if (reverse)
+      gs_pass_kernel<T, true><<<J.nblocks, BX * by, 0, s>>>(J);
+    else
+      gs_pass_kernel<T, false><<<J.nblocks, BX * by, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
 }
 
+// ---- conjugate gradients on level-0 vectors, coefficients kept on the device
+// sc[0] = r.z of the current step, sc[1] = alpha, sc[2] = beta.
+
+namespace {
+
+// per-block FP64 partial sums of a.b and, when c is given, a.c (channel-major)
+template <class T>
+__global__ __launch_bounds__(256) void dot2_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                   const T* __restrict__ c, size_t n,
+                                                   double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  double ab = 0.0, ac = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double av = a[i];
+    ab += av * (double)b[i];
+    if (c) ac += av * (double)c[i];
+  }
+  block_sum_to(ab, s_red, &partials[blockIdx.x]);
+  if (c) block_sum_to(ac, s_red, &partials[gridDim.x + blockIdx.x]);
+}
+
+__global__ void cg_reset_kernel(double* sc) {
+  if (threadIdx.x == 0) {
+    sc[0] = 1.0;
+    sc[1] = 0.0;
+    sc[2] = 0.0;
+  }
+}
+
+// mode 0: the partials hold z.r and z.q of the new preconditioned residual z,
+//   q = -K p of the last direction; beta = alpha z.q / (r.z)_old, the
+//   Polak-Ribiere form z.(r_new - r_old) / (r.z)_old, robust to a preconditioner
+//   that is symmetric only up to rounding; zero on the first step (alpha = 0).
+// mode 1: the partials hold p.q = -p.Kp; alpha = (r.z) / p.Kp, zero on breakdown.
+// mode 2: the partials hold r.r after the update; sc[3] = r.r.
+__global__ __launch_bounds__(256) void cg_coeff_kernel(const double* __restrict__ partials,
+                                                       size_t n_part, int mode, double* sc) {
+  __shared__ double s[256];
+  __shared__ double tot[2];
+  sum_body(SumJob{partials, n_part, mode == 0 ? 2 : 1, tot}, s);
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      const double rz_old = sc[0], alpha = sc[1];
+      sc[2] = (alpha != 0.0 && rz_old != 0.0) ? alpha * tot[1] / rz_old : 0.0;
+      sc[0] = tot[0];
+    } else if (mode == 1) {
+      const double pkp = -tot[0];
+      sc[1] = (pkp > 0.0 && isfinite(pkp)) ? sc[0] / pkp : 0.0;
+    } else {
+      sc[3] = tot[0];
+    }
+  }
+}
+
+// p = z + beta p (p = z on the first step, so p need not start finite)
+template <class T>
+__global__ __launch_bounds__(256) void cg_direction_kernel(T* __restrict__ p, const T* __restrict__ z,
+                                                           const double* __restrict__ sc, size_t n) {
+  const T beta = (T)sc[2];
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = beta == T(0) ? z[i] : z[i] + beta * p[i];
+}
+
+// e += alpha p; r += alpha q (q = -K p), with per-block partial sums of the new r.r
+template <class T>
+__global__ __launch_bounds__(256) void cg_update_kernel(T* __restrict__ e, const T* __restrict__ p,
+                                                        T* __restrict__ r, const T* __restrict__ q,
+                                                        const double* __restrict__ sc, size_t n,
+                                                        double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  const T alpha = (T)sc[1];
+  double rr = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    e[i] += alpha * p[i];
+    const T rn = r[i] + alpha * q[i];
+    r[i] = rn;
+    rr += (double)rn * (double)rn;
+  }
+  block_sum_to(rr, s_red, &partials[blockIdx.x]);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void add_kernel(T* __restrict__ y, const T* __restrict__ x, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) y[i] += x[i];
+}
+
+unsigned dot_blocks(size_t n) { return std::min<unsigned>(grid_stride_blocks(n), 2048); }
+
+}  // namespace
+
+void launch_cg_reset(double* sc, hipStream_t s) {
+  cg_reset_kernel<<<1, 64, 0, s>>>(sc);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_cg_beta(const T* z, const T* r, const T* q, size_t n, double* partials, size_t cap,
+                    double* sc, hipStream_t s) {
+  const unsigned blocks = dot_blocks(n);
+  need_partials(2 * (size_t)blocks, cap);
+  dot2_kernel<T><<<blocks, 256, 0, s>>>(z, r, q, n, partials);
+  MCW_CHECK_LAUNCH();
+  cg_coeff_kernel<<<1, 256, 0, s>>>(partials, blocks, 0, sc);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_cg_alpha(size_t n_part, const double* partials, double* sc, hipStream_t s) {
+  cg_coeff_kernel<<<1, 256, 0, s>>>(partials, n_part, 1, sc);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_add(T* y, const T* x, size_t n, hipStream_t s) {
+  add_kernel<T><<<grid_stride_blocks(n), 256, 0, s>>>(y, x, n);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_cg_direction(T* p, const T* z, const double* sc, size_t n, hipStream_t s) {
+  cg_direction_kernel<T><<<grid_stride_blocks(n), 256, 0, s>>>(p, z, sc, n);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, double* partials,
+                      size_t cap, hipStream_t s) {
+  const unsigned blocks = dot_blocks(n);
+  need_partials(blocks, cap);
+  cg_update_kernel<T><<<blocks, 256, 0, s>>>(e, p, r, q, sc, n, partials);
+  MCW_CHECK_LAUNCH();
+  cg_coeff_kernel<<<1, 256, 0, s>>>(partials, blocks, 2, sc);
+  MCW_CHECK_LAUNCH();
+}
+
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s, int by) {
+                     double* partials, size_t* n_part, hipStream_t s, int by, size_t cap) {
   const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
+  if (partials) need_partials((size_t)J.nblocks, cap);
   if (partials)
     residual_kernel<T, true><<<J.nblocks, BX * by, 0, s>>>(J, partials);
   else
     residual_kernel<T, false><<<J.nblocks, BX * by, 0, s>>>(J, nullptr);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = J.nblocks;
+}
+
+// q = -K p with the per-block partial sums of p.q
+template <class T>
+void launch_neg_apply_dot(const Dims& d, const Faces& fc, const T* st, const T* p, T* q,
+                          double* partials, size_t cap, size_t* n_part, hipStream_t s, int by) {
+  const ColJob J = col_job(d, fc, st, nullptr, const_cast<T*>(p), q, -1, by);
+  need_partials((size_t)J.nblocks, cap);
+  residual_kernel<T, true, true><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  MCW_CHECK_LAUNCH();
+  *n_part = J.nblocks;
 }
 
 template <class T>
@@ -832,9 +1022,17 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 
 #define MCW_INST(T)                                                                             \
   template void launch_smooth_sweep<T>(const Dims&, const Faces&, const T*, const T*, T*,       \
-                                       hipStream_t, int);                                       \
+                                       hipStream_t, int, bool);                                 \
+  template void launch_cg_beta<T>(const T*, const T*, const T*, size_t, double*, size_t,       \
+                                  double*, hipStream_t);                                        \
+  template void launch_add<T>(T*, const T*, size_t, hipStream_t);                              \
+  template void launch_cg_direction<T>(T*, const T*, const double*, size_t, hipStream_t);       \
+  template void launch_cg_update<T>(T*, const T*, T*, const T*, double*, size_t, double*,      \
+                                    size_t, hipStream_t);                                       \
+  template void launch_neg_apply_dot<T>(const Dims&, const Faces&, const T*, const T*, T*,      \
+                                        double*, size_t, size_t*, hipStream_t, int);            \
   template void launch_residual<T>(const Dims&, const Faces&, const T*, const T*, const T*, T*, \
-                                   double*, size_t*, hipStream_t, int);                         \
+                                   double*, size_t*, hipStream_t, int, size_t);                 \
   template void launch_restrict<T>(const Dims&, const Dims&, const Faces&, const DirMapDev&,    \
                                    const DirMapDev&, const DirMapDev&, const T*, T*,            \
                                    hipStream_t);                                                \

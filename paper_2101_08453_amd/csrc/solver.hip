@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <sstream>
+#include <type_traits>
 #include <sys/stat.h>
 #include <unistd.h>
 
@@ -317,33 +318,109 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
   launch_fill<T>(C.x.as<T>(), C.d.N(), T(0), h.stream);
   vcycle<T>(h, l + 1, C.x.as<T>(), C.f.as<T>());
   launch_prolong_dims<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, C.x.as<T>(), x, h.stream);
-  for (int s = 0; s < h.opt.nu_post; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs);
+  // with krylov the post-smoother is the adjoint of the pre-smoother, so the cycle is symmetric
+  for (int s = 0; s < h.opt.nu_post; ++s)
+    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, h.opt.krylov != 0);
+}
+
+// Run `record` on h.stream, or, with use_graph, replay the hipGraph it was
+// captured into on the first call (the buffers it touches are fixed per handle).
+template <class F>
+void replay(mcw_handle& h, hipGraphExec_t& exec, bool& ready, F&& record) {
+  if (!h.opt.use_graph) {
+    record();
+    return;
+  }
+  if (!ready) {
+    hipGraph_t g = nullptr;
+    MCW_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      record();
+    } catch (...) {
+      (void)hipStreamEndCapture(h.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    MCW_HIP(hipStreamEndCapture(h.stream, &g));
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MCW_HIP(e);
+    ready = true;
+  }
+  MCW_HIP(hipGraphLaunch(exec, h.stream));
 }
 
 // One FP32 V-cycle on the level-0 buffers, replayed from a hipGraph when enabled.
 void vcycle_f32(mcw_handle& h) {
   Level& L0 = h.levels[0];
-  if (h.opt.use_graph) {
-    if (!h.vgraph_ready) {
-      hipGraph_t g = nullptr;
-      MCW_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
-      try {
-        vcycle<float>(h, 0, L0.x.as<float>(), L0.f.as<float>());
-      } catch (...) {
-        (void)hipStreamEndCapture(h.stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      MCW_HIP(hipStreamEndCapture(h.stream, &g));
-      const hipError_t e = hipGraphInstantiate(&h.vgraph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      MCW_HIP(e);
-      h.vgraph_ready = true;
+  replay(h, h.vgraph, h.vgraph_ready, [&] { vcycle<float>(h, 0, L0.x.as<float>(), L0.f.as<float>()); });
+}
+
+// ---------------------------------------------------------------- preconditioned CG
+
+// Vectors of the inner CG solve of K e = r: r residual, z = B r (B one
+// symmetric V-cycle from zero), p direction, q = -K p, e correction.
+template <class T>
+struct Krylov {
+  T *r, *z, *p, *q, *e;
+};
+
+template <class T>
+Krylov<T> krylov_vecs(mcw_handle& h) {
+  Level& L0 = h.levels[0];
+  if (std::is_same<T, float>::value)
+    return {L0.f.as<T>(), L0.x.as<T>(), h.kp.as<T>(), h.kq.as<T>(), h.ke.as<T>()};
+  return {h.kr.as<T>(), h.kz.as<T>(), h.kp.as<T>(), h.kq.as<T>(), h.ke.as<T>()};
+}
+
+// One CG step; the coefficients stay on the device (scalars 8..10), so the
+// step is a fixed launch sequence without host synchronisation.
+template <class T>
+void pcg_step(mcw_handle& h, const Krylov<T>& v) {
+  Level& L0 = h.levels[0];
+  const size_t N = L0.d.N();
+  double* sc = h.scalars.as<double>() + 8;
+  double* part = h.partials.as<double>();
+  launch_fill<T>(v.z, N, T(0), h.stream);
+  vcycle<T>(h, 0, v.z, v.r);
+  launch_cg_beta<T>(v.z, v.r, v.q, N, part, h.n_partials, sc, h.stream);
+  launch_cg_direction<T>(v.p, v.z, sc, N, h.stream);
+  size_t np = 0;
+  launch_neg_apply_dot<T>(L0.d, h.faces, stencil_of<T>(L0), v.p, v.q, part, h.n_partials, &np,
+                          h.stream, L0.by_res);
+  launch_cg_alpha(np, part, sc, h.stream);
+  launch_cg_update<T>(v.e, v.p, v.r, v.q, sc, N, part, h.n_partials, h.stream);
+}
+
+// CG steps from e = 0 on the residual in v.r (overwritten): at most m_max, and
+// with rr_stop > 0 only until the recursive r.r falls to rr_stop (read back
+// after every step; one V-cycle outweighs the synchronisation by far).
+// Returns the number of steps taken.
+template <class T>
+int pcg_inner(mcw_handle& h, const Krylov<T>& v, int m_max, double rr_stop) {
+  double* sc = h.scalars.as<double>() + 8;
+  launch_cg_reset(sc, h.stream);
+  launch_fill<T>(v.e, h.levels[0].d.N(), T(0), h.stream);
+  int c = 0;
+  while (c < m_max) {
+    replay(h, h.kgraph, h.kgraph_ready, [&] { pcg_step<T>(h, v); });
+    ++c;
+    if (rr_stop > 0.0) {
+      MCW_HIP(hipMemcpyAsync(h.host_scalars + 3, sc + 3, sizeof(double), hipMemcpyDeviceToHost,
+                             h.stream));
+      MCW_HIP(hipStreamSynchronize(h.stream));
+      const double rr = h.host_scalars[3];
+      if (!(rr > rr_stop)) break;  // reached, or not finite (the outer residual reports it)
     }
-    MCW_HIP(hipGraphLaunch(h.vgraph, h.stream));
-  } else {
-    vcycle<float>(h, 0, L0.x.as<float>(), L0.f.as<float>());
   }
+  return c;
+}
+
+// Steps for the next inner solve: enough to reduce the residual by `target`
+// at the measured rate, within [1, cap].
+int inner_steps(double target, double rho, int cap) {
+  const int m = (int)std::ceil(std::log(target) / std::log(rho));
+  return std::max(1, std::min(m, cap));
 }
 
 // ---------------------------------------------------------------- solve drivers
@@ -368,10 +445,14 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     double* f0 = L0.f.as<double>();
     launch_relayout<double>(h.d, lam, x0, true, h.stream);
     launch_relayout<double>(h.d, h.f64.as<double>(), f0, true, h.stream);
+    const Krylov<double> kv = krylov_vecs<double>(h);
+    double prev_rel = -1.0;
     mcw_status st = MCW_OK;
     for (;;) {
-      launch_residual<double>(L0.d, h.faces, L0.st64.as<double>(), x0, f0, L0.r.as<double>(),
-                              h.partials.as<double>(), &np, h.stream, L0.by_res);
+      // with krylov the residual is the right-hand side of the next inner CG solve
+      launch_residual<double>(L0.d, h.faces, L0.st64.as<double>(), x0, f0,
+                              h.opt.krylov ? kv.r : L0.r.as<double>(), h.partials.as<double>(), &np,
+                              h.stream, L0.by_res, h.n_partials);
       reduce_to_host(h, np, 1, &rr);
       pg.rel = std::sqrt(rr) / fnorm;
       pg.hist.push_back(pg.rel);
@@ -380,8 +461,21 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
       if (!std::isfinite(pg.rel)) { st = MCW_NONFINITE; break; }
       if (pg.rel <= tol) break;
       if (pg.cycles >= h.opt.max_cycles) { st = MCW_NOT_CONVERGED; break; }
-      vcycle<double>(h, 0, x0, f0);
-      ++pg.cycles;
+      if (!h.opt.krylov) {
+        vcycle<double>(h, 0, x0, f0);
+        ++pg.cycles;
+        continue;
+      }
+      // an inner solve that no longer reduces the true residual has stagnated
+      if (prev_rel > 0.0 && pg.rel > 0.95 * prev_rel) { st = MCW_NOT_CONVERGED; break; }
+      // fixed inner_cycles, or until the recursive residual is half the tolerance
+      const int m_max = std::min(h.opt.inner_cycles > 0 ? h.opt.inner_cycles : 100,
+                                 h.opt.max_cycles - pg.cycles);
+      const double stop = h.opt.inner_cycles > 0 ? 0.0 : 0.5 * tol * fnorm;
+      const int m = pcg_inner<double>(h, kv, m_max, stop * stop);
+      launch_add<double>(x0, kv.e, N, h.stream);
+      pg.cycles += m;
+      prev_rel = pg.rel;
     }
     launch_relayout<double>(h.d, x0, lam, false, h.stream);
     return st;
@@ -414,13 +508,9 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
       }
       rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / prev_m)));
     }
-    int m = h.opt.inner_cycles;
-    if (m <= 0) {
-      // reduce to the tolerance in one step, but not below what FP32 can resolve
-      const double target = std::max(tol / pg.rel, 3e-5);
-      m = (int)std::ceil(std::log(target) / std::log(rho_est));
-      m = std::max(1, std::min(m, 12));
-    }
+    // reduce to the tolerance in one step, but not below what FP32 can resolve
+    int m = h.opt.inner_cycles > 0 ? h.opt.inner_cycles
+                                   : inner_steps(std::max(tol / pg.rel, 3e-5), rho_est, 12);
     m = std::min(m, h.opt.max_cycles - pg.cycles);
     // scale the residual by a power of two to O(1) before rounding it to FP32
     const double rms = std::sqrt(rr / nfree);
@@ -429,9 +519,21 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     MCW_HIP(hipMemcpyAsync(scale_dev, &h.host_scalars[7], sizeof(double), hipMemcpyHostToDevice,
                            h.stream));
     launch_scale_to_f32(h.d, h.r64.as<double>(), scale_dev, L0.f.as<float>(), h.stream);
-    launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
-    for (int c = 0; c < m; ++c) vcycle_f32(h);
-    launch_update_lambda(h.d, L0.x.as<float>(), scale_dev, lam, h.stream);
+    if (h.opt.krylov) {
+      // until the scaled FP32 residual has dropped by the same target as above
+      const Krylov<float> kv = krylov_vecs<float>(h);
+      const double target = std::max(tol / pg.rel, 3e-5);
+      const double r0 = std::sqrt(rr) * h.host_scalars[7];
+      const int m_max = std::min(h.opt.inner_cycles > 0 ? h.opt.inner_cycles : 30,
+                                 h.opt.max_cycles - pg.cycles);
+      const double stop = h.opt.inner_cycles > 0 ? 0.0 : target * r0;
+      m = pcg_inner<float>(h, kv, m_max, stop * stop);
+      launch_update_lambda(h.d, kv.e, scale_dev, lam, h.stream);
+    } else {
+      launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
+      for (int c = 0; c < m; ++c) vcycle_f32(h);
+      launch_update_lambda(h.d, L0.x.as<float>(), scale_dev, lam, h.stream);
+    }
     pg.cycles += m;
     prev_m = m;
     prev_rel = pg.rel;
@@ -635,6 +737,8 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
     Fail::arg("bad cycle or smoothing counts");
   if (o.coarsen_rule < 0 || o.coarsen_rule > 2) Fail::arg("bad coarsening rule");
   if (o.coarse_direct_max < 1 || o.coarse_direct_max > 4096) Fail::arg("coarse_direct_max must be in [1, 4096]");
+  if (o.krylov != 0 && o.krylov != 1) Fail::arg("krylov must be 0 or 1");
+  if (o.krylov && o.nu_pre != o.nu_post) Fail::arg("krylov needs nu_pre == nu_post (a symmetric V-cycle)");
 }
 
 void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, mcw_handle& h) {
@@ -765,11 +869,22 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
   h.t64.alloc(N * sizeof(double));
   // per-block partial sums: the largest user is the element-tile grid (2 channels)
   const size_t tiles = (size_t)((h.d.NX() + 14) / 15) * ((h.d.NY() + 14) / 15);
-  const size_t cols = (size_t)((h.d.NX() + 63) / 64) * ((h.d.NY() + 3) / 4);
+  // fine-level column blocks at the smallest tile shape (one row of 64 columns)
+  const size_t cols = (size_t)((h.d.NX() + 63) / 64) * h.d.NY();
   const size_t ecols = (size_t)((h.d.nx + 63) / 64) * ((h.d.ny + 3) / 4);
   h.n_partials = std::max({2 * tiles, cols, 3 * ecols, (size_t)4096});
   h.partials.alloc(h.n_partials * sizeof(double));
-  h.scalars.alloc(8 * sizeof(double));
+  if (opt.krylov) {
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    if (!f32) {
+      h.kr.alloc(N * es);
+      h.kz.alloc(N * es);
+    }
+    h.kp.alloc(N * es);
+    h.kq.alloc(N * es);
+    h.ke.alloc(N * es);
+  }
+  h.scalars.alloc(16 * sizeof(double));
   MCW_HIP(hipHostMalloc((void**)&h.host_scalars, 8 * sizeof(double), hipHostMallocDefault));
   if (opt.autotune) {
     if (f32) autotune_levels<float>(h);
@@ -790,6 +905,7 @@ void destroy_impl(mcw_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   if (h->vgraph) (void)hipGraphExecDestroy(h->vgraph);
+  if (h->kgraph) (void)hipGraphExecDestroy(h->kgraph);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->host_scalars) (void)hipHostFree(h->host_scalars);
@@ -833,8 +949,10 @@ void smooth_t(mcw_handle& h, int l, T* x, const T* f, int sweeps) {
   Level& L = level_at(&h, l, false);
   launch_relayout<T>(L.d, x, L.x.as<T>(), true, h.stream);
   launch_relayout<T>(L.d, f, L.f.as<T>(), true, h.stream);
-  for (int s = 0; s < sweeps; ++s)
-    launch_smooth_sweep<T>(L.d, h.faces, stencil_of<T>(L), L.f.as<T>(), L.x.as<T>(), h.stream);
+  const bool reverse = sweeps < 0;
+  for (int s = 0; s < std::abs(sweeps); ++s)
+    launch_smooth_sweep<T>(L.d, h.faces, stencil_of<T>(L), L.f.as<T>(), L.x.as<T>(), h.stream,
+                           L.by_gs, reverse);
   launch_relayout<T>(L.d, L.x.as<T>(), x, false, h.stream);
 }
 
@@ -1343,8 +1461,10 @@ mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) Fail::arg("a handle appears twice in the batch");
   }
-  if (hs[0]->opt.precision != MCW_FP32_REFINE) {
-    // plain FP64 handles are solved one after another
+  bool any_krylov = false;
+  for (int i = 0; i < m; ++i) any_krylov = any_krylov || hs[i]->opt.krylov;
+  if (hs[0]->opt.precision != MCW_FP32_REFINE || any_krylov) {
+    // plain FP64 and CG handles are solved one after another
     mcw_status first = MCW_OK;
     for (int i = 0; i < m; ++i) {
       const mcw_status s = solve_impl(*hs[i], u0[i], lambda[i], u ? u[i] : nullptr,
@@ -1377,6 +1497,7 @@ void mcw_default_options(mcw_options* o) {
   o->use_graph = 1;
   o->verbose = std::getenv("MCW_LOG") ? 1 : 0;
   o->autotune = 1;
+  o->krylov = 0;
 }
 
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
@@ -1573,7 +1694,7 @@ mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out) {
 mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t sweeps) {
   if (!h) return MCW_INVALID_ARG;
   return guarded(h, [&] {
-    if (!x || !f || sweeps < 0) Fail::arg("bad smoother arguments");
+    if (!x || !f || sweeps < -1000 || sweeps > 1000) Fail::arg("bad smoother arguments");
     if (is_f32(h)) smooth_t(*h, l, static_cast<float*>(x), static_cast<const float*>(f), sweeps);
     else smooth_t(*h, l, static_cast<double*>(x), static_cast<const double*>(f), sweeps);
     MCW_HIP(hipStreamSynchronize(h->stream));

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("nu_post", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
                 ("coarsen_rule", ctypes.c_int32), ("coarse_direct_max", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32),
+                ("krylov", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -155,7 +156,8 @@ class Grid:
 
     def __init__(self, X, Y, Z, a, gamma=GAMMA_BOTTOM, precision="fp32_refine", rtol=1e-8,
                  max_cycles=200, nu_pre=2, nu_post=2, inner_cycles=0, coarsen_rule="operator",
-                 coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True):
+                 coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True,
+                 krylov=False):
         L = lib()
         self._h = H()
         nzp, nyp, nxp = X.shape
@@ -182,6 +184,7 @@ class Grid:
         o.coarse_direct_max = coarse_direct_max
         o.use_graph = 1 if use_graph else 0
         o.autotune = 1 if autotune else 0
+        o.krylov = 1 if krylov else 0
         o.verbose = 1 if (verbose or os.environ.get("MCW_LOG")) else 0
         self.precision = precision
         self.vdtype = torch.float32 if precision == "fp32_refine" else torch.float64
@@ -319,6 +322,7 @@ class Grid:
         return out
 
     def smooth(self, l, x, f, sweeps=1):
+        """sweeps > 0 forward Gauss-Seidel sweeps, < 0 reverse (adjoint) sweeps."""
         s = self.level_shape(l)
         self._check(lib().mcw_smooth(self._h, l, _ptr(x, self.vdtype, s, "x"),
                                      _ptr(f, self.vdtype, s, "f"), sweeps))

@@ -218,3 +218,26 @@ def test_autotuned_tile_shapes_are_cached_and_do_not_change_results(tmp_path, mo
     a, ua, _ = g1.solve(u0)
     b, ub, _ = g2.solve(u0)
     assert torch.equal(a, b) and torch.equal(ua, ub)
+
+
+@pytest.mark.parametrize("precision,krylov", [("fp64", False), ("fp64", True), ("fp32_refine", True)])
+def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precision, krylov):
+    """With one row of 64 columns per block the fine residual has the most
+    blocks (10 x 601 here, more than the element tiles need); each block
+    leaves a partial sum, which must fit the handle's buffer."""
+    mcwind = _mcw()
+    cache = tmp_path / "tune.json"
+    tag = "f64" if precision == "fp64" else "f32"
+    cache.write_text('{\n  "gfx950|gs|601x601x3|%s": 1,\n  "gfx950|res|601x601x3|%s": 1\n}\n'
+                     % (tag, tag))
+    monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
+    p = inputs.hills_problem(600, 600, 2, 4, 8, a=(1.0, 1.0, 2.0))
+    print(f"[case] 600x600x2 {precision} krylov={krylov} one-row tiles", flush=True)
+    g, u0 = mcwind.grid_from_problem(p, precision=precision, krylov=krylov, rtol=1e-10)
+    assert g.tile_rows(0) == (1, 1)
+    lam, _, info = g.solve(u0, want_u=False)
+    assert info["rel_residual"] <= 1e-10
+    g2, _ = mcwind.grid_from_problem(p, precision=precision, krylov=krylov, rtol=1e-10,
+                                     autotune=False)
+    lam2, _, _ = g2.solve(u0, want_u=False)
+    assert float((lam - lam2).abs().max() / lam2.abs().max()) < 1e-8
