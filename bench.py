@@ -121,7 +121,7 @@ def kernel_table(g, stream, n_free):
     return out
 
 
-def cpu_baseline(p, du, n_sample=192):
+def cpu_baseline(p, du, n_sample=240):
     """The FP64 oracle (as it stands) on a bounded window of the same workload:
     the first n_sample x n_sample element columns of the perturbed wind problem."""
     from threadpoolctl import threadpool_limits
