@@ -227,6 +227,39 @@ def c5(seed=5, n=512, nz=15):
     return fractal_problem(n, n, nz, 500.0, seed, name=f"{n}x{n}x{nz} fractal 500 m")
 
 
+def coarse_wind(Lx, Ly, spacing=600.0, nl=30, seed=60, s_ref=8.0, first=25.0, ratio=1.15,
+                z0=0.1, noise=0.3):
+    """A stand-in for the atmospheric model's wind over a Lx x Ly domain:
+    columns every `spacing` m from -spacing/2 (the domain lies inside the
+    column grid), nl terrain-following levels from `first` m above ground
+    growing by `ratio`, scaled per column by a smooth factor in [0.9, 1.1];
+    log-law speed (s_ref at 10 m, roughness z0) turning 30 degrees from the
+    ground to the top and veering +-20 degrees across the domain, vertical
+    component 0, plus N(0, noise) in every component.
+    Returns dict(x0, y0, dx, dy, hagl (nl, ncy, ncx), wind (3, nl, ncy, ncx), z0)."""
+    rng = np.random.default_rng(seed)
+    ncx = int(math.ceil(Lx / spacing)) + 2
+    ncy = int(math.ceil(Ly / spacing)) + 2
+    x0 = y0 = -0.5 * spacing
+    xs = x0 + spacing * np.arange(ncx)
+    ys = y0 + spacing * np.arange(ncy)
+    base = first * np.cumprod(np.concatenate([[1.0], np.full(nl - 1, ratio)]))
+    phase = rng.uniform(0.0, 2.0 * math.pi, 2)
+    fac = 1.0 + 0.1 * np.sin(2.0 * math.pi * xs[None, :] / 7000.0 + phase[0]) \
+        * np.cos(2.0 * math.pi * ys[:, None] / 9000.0 + phase[1])
+    hagl = base[:, None, None] * fac[None]
+    speed = s_ref * np.log(hagl / z0) / math.log(10.0 / z0)
+    turn = (math.pi / 6.0) * (hagl - hagl[0]) / (hagl[-1] - hagl[0])
+    veer = (math.pi / 9.0) * np.sin(2.0 * math.pi * xs / max(Lx, spacing))[None, None, :]
+    theta = rng.uniform(0.0, 2.0 * math.pi) + turn + veer
+    wind = np.zeros((3, nl, ncy, ncx))
+    wind[0] = speed * np.cos(theta)
+    wind[1] = speed * np.sin(theta)
+    wind += rng.normal(0.0, noise, size=wind.shape)
+    return {"x0": x0, "y0": y0, "dx": spacing, "dy": spacing,
+            "hagl": np.ascontiguousarray(hagl), "wind": np.ascontiguousarray(wind), "z0": z0}
+
+
 def fire_mask(nx, ny, dx=30.0, dy=30.0, seed=55):
     """Elliptical fire-perimeter mask over the bottom-layer element centres, (ny, nx) bool."""
     rng = np.random.default_rng(seed)
