@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-kernels", action="store_true", help="skip per-kernel timing")
     ap.add_argument("--no-krylov", action="store_true",
                     help="skip the multigrid-preconditioned CG comparison")
+    ap.add_argument("--no-coupling", action="store_true",
+                    help="skip timing the steps around the solve")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules"],
                     help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
                          "rules: coarsening rules across penalties and layer stretching")
@@ -353,6 +355,25 @@ def main():
             kernels = kernel_table(g, stream, n_free)
             for k, v in kernels.items():
                 log(f"kernel {k}: {v['ms']:.3f} ms, {v['GB/s']:.0f} GB/s")
+        coupling = None
+        if not args.no_coupling:
+            # the steps around the solve: a coarse wind every 600 m (40 levels) to the
+            # element centres, and the wind at 6.1 m above ground from the solved wind
+            cw = inputs.coarse_wind(30.0 * n, 30.0 * n, spacing=600.0, nl=40)
+            cwd = dict(cw, hagl=torch.from_numpy(cw["hagl"]).to(dev),
+                       wind=torch.from_numpy(cw["wind"]).to(dev))
+            g.interp_wind(cwd)
+            ms_i = time_on_stream(stream, lambda: g.interp_wind(cwd), 3)
+            g.surface_wind(u0p, 6.1)
+            ms_s = time_on_stream(stream, lambda: g.surface_wind(u0p, 6.1), 3)
+            # each node's coordinates once and u0 written once; the coarse wind once
+            b_i = 24.0 * N + 24.0 * E + 8.0 * (cw["hagl"].size + cw["wind"].size)
+            coupling = {"interp_ms": round(ms_i, 3), "interp_GB/s": round(b_i / ms_i / 1e6, 1),
+                        "surface_ms": round(ms_s, 3),
+                        "coarse_wind": f"{cw['hagl'].shape[2]}x{cw['hagl'].shape[1]} columns, "
+                                       f"{cw['hagl'].shape[0]} levels"}
+            log(f"coupling: interpolation {ms_i:.2f} ms ({b_i / ms_i / 1e6:.0f} GB/s), "
+                f"surface wind {ms_s:.3f} ms")
         del g
         torch.cuda.empty_cache()
         krylov = None
@@ -440,6 +461,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "mg_pcg": krylov,
+        "coupling": coupling,
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }

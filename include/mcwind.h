@@ -206,6 +206,38 @@ mcw_status mcw_recover(mcw_handle* h, const double* u0, const double* lambda, do
 mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda, double* D,
                           double* rel);
 
+/* ---- steps on either side of the solve (coupled fire-atmosphere model) ----
+ * The solve takes the place of plainly interpolating the atmospheric model's
+ * wind to the fire model's grid (Sec. 1).  These two calls are that
+ * interpolation, giving the solve's u0, and the fire model's read-out of the
+ * solved wind.  Heights are above the ground: an element centre (the mean of
+ * its 8 corner nodes) minus the mean height of its column's 4 bottom nodes.
+ * Vertically, values are linear in height between levels, equal to the top
+ * level above it, and follow the neutral log law v(h1) ln(z/z0) / ln(h1/z0)
+ * below the lowest level h1 (0 at z <= z0). */
+typedef struct {
+  int32_t ncx, ncy;      /* coarse columns along x and y, >= 2 each */
+  int32_t nl;            /* levels per column, >= 1 */
+  double x0, y0;         /* horizontal position of column (0, 0) */
+  double dx, dy;         /* column spacing, > 0 */
+  double z0;             /* roughness length of the log law, > 0 */
+  const double* hagl;    /* device, (nl, ncy, ncx): level heights above ground, increasing
+                            up each column, all > z0 */
+  const double* wind;    /* device, (3, nl, ncy, ncx): wind components at the levels */
+} mcw_coarse_wind;
+
+/* u0 (device, (3, nz, ny, nx)) at the element centres from the coarse wind:
+ * at each centre, the wind of the four coarse columns around it (bilinear
+ * weights; positions outside the column grid take its edge) at the centre's
+ * height above ground.  MCW_INVALID_ARG if the level heights do not increase
+ * or do not start above z0. */
+mcw_status mcw_interp_wind(mcw_handle* h, const mcw_coarse_wind* cw, double* u0);
+
+/* uv (device, (2, ny, nx)): the horizontal wind u[0], u[1] (device,
+ * (3, nz, ny, nx), element centres) at `height` > 0 above the ground over
+ * each element column, by the vertical rule above on the column's centres. */
+mcw_status mcw_surface_wind(mcw_handle* h, const double* u, double height, double z0, double* uv);
+
 /* Number of levels, and the dimensions of level l (host int32[3]: nx, ny, nz),
  * whether it coarsens horizontally towards level l+1 (host int32, may be NULL)
  * and its kept node planes (host int32[nz+1], may be NULL; count written to

@@ -77,37 +77,54 @@ def bilinear_cell(pos, origin, spacing, n):
     return i, s - i
 
 
+def element_centre(X, Y, Z, k, j, i):
+    """Centre (x, y, z) of element (i, j, k) and the ground height under it."""
+    sl = (slice(k, k + 2), slice(j, j + 2), slice(i, i + 2))
+    c = np.array([X[sl].mean(), Y[sl].mean(), Z[sl].mean()])
+    return c, Z[0, j:j + 2, i:i + 2].mean()
+
+
+def interp_wind_element(X, Y, Z, cw, k, j, i):
+    """u0 (3,) at the centre of element (i, j, k) from the coarse wind
+    cw = dict(x0, y0, dx, dy, hagl (nl, ncy, ncx), wind (3, nl, ncy, ncx), z0)."""
+    c, zs = element_centre(X, Y, Z, k, j, i)
+    zeta = c[2] - zs
+    hagl, wind = cw["hagl"], cw["wind"]
+    _, ncy, ncx = hagl.shape
+    I, a = bilinear_cell(c[0], cw["x0"], cw["dx"], ncx)
+    J, b = bilinear_cell(c[1], cw["y0"], cw["dy"], ncy)
+    acc = np.zeros(3)
+    for (dI, dJ, w) in ((0, 0, (1 - a) * (1 - b)), (1, 0, a * (1 - b)),
+                        (0, 1, (1 - a) * b), (1, 1, a * b)):
+        acc += w * column_profile(hagl[:, J + dJ, I + dI], wind[:, :, J + dJ, I + dI], zeta, cw["z0"])
+    return acc
+
+
 def interp_wind(X, Y, Z, cw):
-    """u0 (3, nz, ny, nx) at the element centres from the coarse wind
-    cw = dict(x0, y0, dx, dy, hagl (nl, ncy, ncx), wind (3, nl, ncy, ncx), z0).
-    Loops over elements: for small grids."""
-    c, zeta = heights_above_ground(X, Y, Z)
-    nz, ny, nx = zeta.shape
-    hagl, wind, z0 = cw["hagl"], cw["wind"], cw["z0"]
-    nl, ncy, ncx = hagl.shape
+    """u0 (3, nz, ny, nx) at every element centre (loops: for small grids)."""
+    nz, ny, nx = (s - 1 for s in X.shape)
     u0 = np.zeros((3, nz, ny, nx))
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
-                I, a = bilinear_cell(c[0, k, j, i], cw["x0"], cw["dx"], ncx)
-                J, b = bilinear_cell(c[1, k, j, i], cw["y0"], cw["dy"], ncy)
-                acc = np.zeros(3)
-                for (dI, dJ, w) in ((0, 0, (1 - a) * (1 - b)), (1, 0, a * (1 - b)),
-                                    (0, 1, (1 - a) * b), (1, 1, a * b)):
-                    col = column_profile(hagl[:, J + dJ, I + dI], wind[:, :, J + dJ, I + dI],
-                                         zeta[k, j, i], z0)
-                    acc += w * col
-                u0[:, k, j, i] = acc
+                u0[:, k, j, i] = interp_wind_element(X, Y, Z, cw, k, j, i)
     return u0
 
 
+def surface_wind_column(X, Y, Z, u, height, z0, j, i):
+    """(2,): horizontal wind at `height` above ground over element column (i, j),
+    from the wind u (3, nz, ny, nx) at the element centres."""
+    nz = X.shape[0] - 1
+    zeta = np.array([element_centre(X, Y, Z, k, j, i)[0][2] for k in range(nz)])
+    zeta -= Z[0, j:j + 2, i:i + 2].mean()
+    return column_profile(zeta, u[:2, :, j, i], height, z0)
+
+
 def surface_wind(X, Y, Z, u, height, z0):
-    """(2, ny, nx): horizontal wind at `height` above ground over each element
-    column, from the wind u (3, nz, ny, nx) at the element centres."""
-    _, zeta = heights_above_ground(X, Y, Z)
-    nz, ny, nx = zeta.shape
+    """(2, ny, nx) over every element column (loops: for small grids)."""
+    nz, ny, nx = (s - 1 for s in X.shape)
     out = np.zeros((2, ny, nx))
     for j in range(ny):
         for i in range(nx):
-            out[:, j, i] = column_profile(zeta[:, j, i], u[:2, :, j, i], height, z0)
+            out[:, j, i] = surface_wind_column(X, Y, Z, u, height, z0, j, i)
     return out

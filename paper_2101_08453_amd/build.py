@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcwind.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["elem_kernels.hip", "mg_kernels.hip", "solver.hip"]
+SOURCES = ["elem_kernels.hip", "mg_kernels.hip", "coupling_kernels.hip", "solver.hip"]
 
 # Packed FP32 instructions are disabled on purpose (the compiler would form
 # them from float2 / paired scalar code).

@@ -298,6 +298,10 @@ void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partia
 void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
                        double* partials, size_t* n_part);
 void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u);
+// Steps around the solve (coupling_kernels.hip)
+bool launch_coarse_check(const mcw_handle& h, const mcw_coarse_wind& cw);
+void launch_interp_wind(const mcw_handle& h, const mcw_coarse_wind& cw, double* u0);
+void launch_surface_wind(const mcw_handle& h, const double* u, double height, double z0, double* uv);
 void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_lam, double* partials,
                             size_t* n_part);
 void launch_adjoint_elements(const mcw_handle& h, const double* g_u, const double* lam,

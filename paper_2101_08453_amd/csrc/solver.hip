@@ -1630,6 +1630,35 @@ mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda,
   });
 }
 
+mcw_status mcw_interp_wind(mcw_handle* h, const mcw_coarse_wind* cw, double* u0) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!cw || !u0 || !cw->hagl || !cw->wind) Fail::arg("null coarse wind or output");
+    if (cw->ncx < 2 || cw->ncy < 2 || cw->nl < 1) Fail::arg("need ncx, ncy >= 2 and nl >= 1");
+    const double v[5] = {cw->x0, cw->y0, cw->dx, cw->dy, cw->z0};
+    for (double x : v)
+      if (!std::isfinite(x)) Fail::arg("coarse grid origin, spacing and z0 must be finite");
+    if (!(cw->dx > 0.0) || !(cw->dy > 0.0) || !(cw->z0 > 0.0)) Fail::arg("dx, dy and z0 must be > 0");
+    if (!launch_coarse_check(*h, *cw))
+      Fail::arg("coarse level heights must be finite, increase up each column and start above z0");
+    launch_interp_wind(*h, *cw, u0);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
+mcw_status mcw_surface_wind(mcw_handle* h, const double* u, double height, double z0, double* uv) {
+  if (!h) return MCW_INVALID_ARG;
+  return guarded(h, [&] {
+    if (!u || !uv) Fail::arg("null wind or output");
+    if (!(height > 0.0) || !std::isfinite(height) || !(z0 > 0.0) || !std::isfinite(z0))
+      Fail::arg("height and z0 must be finite and > 0");
+    launch_surface_wind(*h, u, height, z0, uv);
+    MCW_HIP(hipStreamSynchronize(h->stream));
+    return MCW_OK;
+  });
+}
+
 mcw_status mcw_tile_shape(const mcw_handle* hc, int32_t l, int32_t* rows_smooth, int32_t* rows_residual) {
   auto* h = const_cast<mcw_handle*>(hc);
   if (!h) return MCW_INVALID_ARG;

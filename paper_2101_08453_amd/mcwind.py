@@ -72,6 +72,13 @@ class Info(ctypes.Structure):
         }
 
 
+class CoarseWind(ctypes.Structure):
+    _fields_ = [("ncx", ctypes.c_int32), ("ncy", ctypes.c_int32), ("nl", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("z0", ctypes.c_double), ("hagl", ctypes.c_void_p),
+                ("wind", ctypes.c_void_p)]
+
+
 class MCWError(RuntimeError):
     def __init__(self, status, message):
         self.status = status
@@ -109,6 +116,8 @@ SIGNATURES = {
     "mcw_coarse_solve": (I32, [H, P, P]),
     "mcw_vcycle": (I32, [H, P, P]),
     "mcw_run_kernel": (I32, [H, I32, I32, I32]),
+    "mcw_interp_wind": (I32, [H, ctypes.POINTER(CoarseWind), P]),
+    "mcw_surface_wind": (I32, [H, P, ctypes.c_double, ctypes.c_double, P]),
     "mcw_tile_shape": (I32, [H, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "mcw_status_string": (ctypes.c_char_p, [I32]),
     "mcw_last_error": (ctypes.c_char_p, [H]),
@@ -290,6 +299,31 @@ class Grid:
                                          _ptr(D, torch.float64, self.node_shape, "D"),
                                          ctypes.byref(rel)))
         return D, rel.value
+
+    # ------------------------------------------------------------ around the solve
+    def interp_wind(self, cw):
+        """u0 (3, nz, ny, nx) at the element centres from a coarse wind given as a
+        dict with x0, y0, dx, dy, z0 (floats) and device float64 tensors hagl
+        (nl, ncy, ncx) and wind (3, nl, ncy, ncx)."""
+        hagl, wind = cw["hagl"], cw["wind"]
+        nl, ncy, ncx = hagl.shape
+        c = CoarseWind()
+        c.ncx, c.ncy, c.nl = ncx, ncy, nl
+        c.x0, c.y0, c.dx, c.dy, c.z0 = (float(cw[k]) for k in ("x0", "y0", "dx", "dy", "z0"))
+        c.hagl = _ptr(hagl, torch.float64, (nl, ncy, ncx), "hagl")
+        c.wind = _ptr(wind, torch.float64, (3, nl, ncy, ncx), "wind")
+        u0 = torch.empty(self.elem_shape, dtype=torch.float64, device=self.device)
+        self._check(lib().mcw_interp_wind(self._h, ctypes.byref(c),
+                                          _ptr(u0, torch.float64, self.elem_shape, "u0")))
+        return u0
+
+    def surface_wind(self, u, height, z0=0.1):
+        """(2, ny, nx): horizontal wind at `height` above ground over each column."""
+        uv = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        self._check(lib().mcw_surface_wind(self._h, _ptr(u, torch.float64, self.elem_shape, "u"),
+                                           float(height), float(z0),
+                                           _ptr(uv, torch.float64, (2, self.ny, self.nx), "uv")))
+        return uv
 
     def num_levels(self):
         return int(lib().mcw_num_levels(self._h))
