@@ -278,13 +278,17 @@ mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
 
 /* Run `reps` launches of one multigrid kernel on level l's own buffers (their
  * current contents; no layout conversion, no allocation) and wait: kernel 0 =
- * one Gauss-Seidel sweep (4 colour passes), 1 = residual, 2 = restriction to
+ * one Gauss-Seidel sweep (4 colour passes, in 2 launches when the level uses
+ * the fused two-colour pass), 1 = residual, 2 = restriction to
  * level l+1, 3 = prolongation from level l+1, 4 = FP64 matrix-free residual
  * f - K lambda on the fine grid (l must be 0).  For timing and profiling. */
 mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps);
 
-/* Tile rows per block (blocks are 64 x rows columns) used on level l by the
- * Gauss-Seidel colour pass and by the residual (host int32 outputs). */
+/* Tile shape used on level l by the Gauss-Seidel colour pass and by the
+ * residual (host int32 outputs): rows of 64 columns per block, and for the
+ * colour pass 0 when it runs fused, two colours per launch with one block per
+ * row of the grid (the autotuner's choice; default 0 for the colour pass and
+ * 4 for the residual). */
 mcw_status mcw_tile_shape(const mcw_handle* h, int32_t l, int32_t* rows_smooth, int32_t* rows_residual);
 
 /* ---- errors ---- */

@@ -243,7 +243,9 @@ struct Level {
   DirMap mx, my, mz;        // to the next coarser level
   DevBuf maps;              // device copies of the three DirMaps
   DirMapDev dmx{}, dmy{}, dmz{};
-  int by_gs = 4, by_res = 4;  // tuned tile rows of the colour pass and the residual
+  // tuned tile shapes: rows of 64 columns per block of the colour pass (0: the
+  // fused two-colour pass, one block per row) and of the residual
+  int by_gs = 0, by_res = 4;
   double h1 = 0, h2 = 0;
   std::vector<double> h3;
 };

@@ -37,23 +37,29 @@ __device__ __forceinline__ StLayout dev_layout(int NX, int NY) {
   return L;
 }
 
-// The SW stencil values of node p, read as 16-byte groups that lie 1 KB apart.
-__device__ __forceinline__ void load_stencil(const float* __restrict__ st, size_t p, float a[SW]) {
-  const float4* v = reinterpret_cast<const float4*>(st) + (p >> 6) * (SW / 4) * 64 + (p & 63);
+// The SW stencil values of node p, read as 16-byte groups that lie 1 KB apart,
+// with non-temporal loads: a pass streams each stencil value once, so it
+// should not displace the x values that neighbouring columns reuse.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_stencil_nt(const float* __restrict__ st, size_t p, float a[SW]) {
+  const f32x4* v = reinterpret_cast<const f32x4*>(st) + (p >> 6) * (SW / 4) * 64 + (p & 63);
 #pragma unroll
   for (int g = 0; g < SW / 4; ++g) {
-    const float4 t = v[g * 64];
+    const f32x4 t = __builtin_nontemporal_load(v + g * 64);
     a[4 * g] = t.x; a[4 * g + 1] = t.y; a[4 * g + 2] = t.z; a[4 * g + 3] = t.w;
   }
 }
-__device__ __forceinline__ void load_stencil(const double* __restrict__ st, size_t p, double a[SW]) {
-  const double2* v = reinterpret_cast<const double2*>(st) + (p >> 6) * (SW / 2) * 64 + (p & 63);
+__device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, size_t p, double a[SW]) {
+  const f64x2* v = reinterpret_cast<const f64x2*>(st) + (p >> 6) * (SW / 2) * 64 + (p & 63);
 #pragma unroll
   for (int g = 0; g < SW / 2; ++g) {
-    const double2 t = v[g * 64];
+    const f64x2 t = __builtin_nontemporal_load(v + g * 64);
     a[2 * g] = t.x; a[2 * g + 1] = t.y;
   }
 }
+template <class T>
+__device__ __forceinline__ T load_nt(const T* p) { return __builtin_nontemporal_load(p); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so that neighbouring tiles share an L2.
@@ -96,20 +102,16 @@ __device__ __forceinline__ void block_sum_to(double v, double* s_red, double* ou
 
 // ---------------------------------------------------------------- smoother
 
-// One colour pass: every column (i, j) with i = ci mod 2, j = cj mod 2 runs
-// pointwise Gauss-Seidel from the bottom to the top.  Neighbour columns belong
-// to other colours and are not changed during the pass; the value below is
-// this thread's own freshly updated one.
-template <class T, bool REV = false>
-__device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
+// Pointwise Gauss-Seidel down one column (i, j) of the colour in J: bottom to
+// top, or top to bottom for the reverse (adjoint) sweep.  Neighbour columns
+// belong to other colours and are not changed meanwhile; the value below (or
+// above) is this thread's own freshly updated one.
+template <class T, bool REV>
+__device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
   const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
-  const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
-  const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
-  if (ii >= J.ncx || jj >= J.ncy) return;
-  const int i = 2 * ii + J.ci, j = 2 * jj + J.cj;
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) return;
   const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
   const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
@@ -120,74 +122,69 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
                        j * NX + sp, jp * NX + sm, jp * NX + s0, jp * NX + sp};
   const size_t plane = (size_t)NX * NY;
   const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
-  T xm[9], x0[9], xp[9];
-  if (!REV) {
-    // bottom to top: the value below is this thread's fresh one
-    {
-      const size_t pm = (size_t)(kf > 0 ? kf - 1 : 0) * plane, p0 = (size_t)kf * plane;
+  // rolling window of the 3 x 9 neighbour values: xl the plane already passed,
+  // x0 the current plane, xn the plane ahead
+  T xl[9], x0[9], xn[9];
+  {
+    const int k0 = REV ? kl : kf;
+    const int kb = REV ? (kl + 1 < NZ ? kl + 1 : NZ - 1) : (kf > 0 ? kf - 1 : 0);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        xm[q] = x[pm + cols[q]];
-        x0[q] = x[p0 + cols[q]];
-      }
-    }
-    for (int k = kf; k <= kl; ++k) {
-      const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
-      T a[SW];
-      load_stencil(st, L.node(i, j, k), a);
-      T s = f[(size_t)k * plane + cols[4]];
-#pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        if (o == 13) continue;
-        const int dk = o / 9, q = o % 9;
-        const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
-        s -= a[o] * xv;
-      }
-      const T xn = s / a[13];
-      x[(size_t)k * plane + cols[4]] = xn;
-      x0[4] = xn;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        xm[q] = x0[q];
-        x0[q] = xp[q];
-      }
-    }
-  } else {
-    // top to bottom (the adjoint sweep of a symmetric V-cycle)
-    {
-      const size_t pp = (size_t)(kl + 1 < NZ ? kl + 1 : NZ - 1) * plane, p0 = (size_t)kl * plane;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        xp[q] = x[pp + cols[q]];
-        x0[q] = x[p0 + cols[q]];
-      }
-    }
-    for (int k = kl; k >= kf; --k) {
-      const size_t pm = (size_t)(k > 0 ? k - 1 : 0) * plane;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) xm[q] = x[pm + cols[q]];
-      T a[SW];
-      load_stencil(st, L.node(i, j, k), a);
-      T s = f[(size_t)k * plane + cols[4]];
-#pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        if (o == 13) continue;
-        const int dk = o / 9, q = o % 9;
-        const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
-        s -= a[o] * xv;
-      }
-      const T xn = s / a[13];
-      x[(size_t)k * plane + cols[4]] = xn;
-      x0[4] = xn;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        xp[q] = x0[q];
-        x0[q] = xm[q];
-      }
+    for (int q = 0; q < 9; ++q) {
+      xl[q] = x[(size_t)kb * plane + cols[q]];
+      x0[q] = x[(size_t)k0 * plane + cols[q]];
     }
   }
+  for (int t = 0; t <= kl - kf; ++t) {
+    const int k = REV ? kl - t : kf + t;
+    const int ka = REV ? (k > 0 ? k - 1 : 0) : (k + 1 < NZ ? k + 1 : NZ - 1);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) xn[q] = x[(size_t)ka * plane + cols[q]];
+    T a[SW];
+    load_stencil_nt(st, L.node(i, j, k), a);
+    T s = load_nt(f + (size_t)k * plane + cols[4]);
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      if (o == 13) continue;
+      const int dk = o / 9, q = o % 9;
+      // dk = 0 is the plane below, 2 the plane above
+      const T* lo = REV ? xn : xl;
+      const T* hi = REV ? xl : xn;
+      const T xv = dk == 0 ? lo[q] : (dk == 1 ? x0[q] : hi[q]);
+      s -= a[o] * xv;
+    }
+    const T xnew = s / a[13];
+    x[(size_t)k * plane + cols[4]] = xnew;
+    x0[4] = xnew;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      xl[q] = x0[q];
+      x0[q] = xn[q];
+    }
+  }
+}
+
+// One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
+// tiles of 64 x J.by columns per block.
+template <class T, bool REV = false>
+__device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
+  const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
+  const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
+  if (ii >= J.ncx || jj >= J.ncy) return;
+  gs_column<T, REV>(J, 2 * ii + J.ci, 2 * jj + J.cj);
+}
+
+// Two colour passes of the same rows in one launch: colour J0 then colour J1
+// on every row j = cj mod 2, one block per row.  The J1 columns of a row couple
+// only to the J0 columns of the same row (and to untouched rows j +- 1), so a
+// block barrier between the two halves keeps the order of the separate passes
+// and gives the same result bit for bit, while x of rows j-1, j, j+1 is
+// fetched once for both colours.
+template <class T, bool REV>
+__global__ __launch_bounds__(1024) void gs_fused_kernel(ColJob J0, ColJob J1) {
+  const int j = 2 * (int)blockIdx.x + J0.cj;
+  for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x) gs_column<T, REV>(J0, 2 * ii + J0.ci, j);
+  __syncthreads();
+  for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x) gs_column<T, REV>(J1, 2 * ii + J1.ci, j);
 }
 
 template <class T, bool REV>
@@ -247,8 +244,8 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
     T a[SW];
-    load_stencil(st, L.node(i, j, k), a);
-    T s = f ? f[(size_t)k * plane + own] : T(0);
+    load_stencil_nt(st, L.node(i, j, k), a);
+    T s = f ? load_nt(f + (size_t)k * plane + own) : T(0);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       const int dk = o / 9, q = o % 9;
@@ -677,6 +674,23 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
                          hipStream_t s, int by, bool reverse) {
+  if (by == 0) {
+    // colours (0,0),(1,0) then (0,1),(1,1); reversed: (1,1),(0,1) then (1,0),(0,0)
+    for (int pr = 0; pr < 2; ++pr) {
+      const int c0 = reverse ? 3 - 2 * pr : 2 * pr, c1 = reverse ? c0 - 1 : c0 + 1;
+      const ColJob J0 = col_job(d, fc, st, f, x, nullptr, c0, 1);
+      const ColJob J1 = col_job(d, fc, st, f, x, nullptr, c1, 1);
+      if (J0.ncy <= 0) continue;
+      const int cols = std::max(J0.ncx, J1.ncx);
+      const int threads = std::min(1024, std::max(64, (cols + 63) / 64 * 64));
+      if (reverse)
+        gs_fused_kernel<T, true><<<J0.ncy, threads, 0, s>>>(J0, J1);
+      else
+        gs_fused_kernel<T, false><<<J0.ncy, threads, 0, s>>>(J0, J1);
+      MCW_CHECK_LAUNCH();
+    }
+    return;
+  }
   for (int cc = 0; cc < 4; ++cc) {
     const int c = reverse ? 3 - cc : cc;
     const ColJob J = col_job(d, fc, st, f, x, nullptr, c, by);

@@ -670,13 +670,15 @@ void autotune_levels(mcw_handle& h) {
   MCW_HIP(hipGetDeviceProperties(&prop, h.device));
   const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
   TuneCache cache;
-  const int cand[3] = {1, 2, 4};
+  // colour pass: 0 = fused two-colour pass (one block per row), or 1, 2, 4 rows
+  // of 64 columns per block of the four separate passes; residual: 1, 2, 4 rows
+  const std::vector<int> cand_gs = {0, 1, 2, 4}, cand_res = {1, 2, 4};
   for (auto& L : h.levels) {
     if (L.d.N() < (size_t)1 << 16) continue;
     const std::string dims = std::to_string(L.d.NX()) + "x" + std::to_string(L.d.NY()) + "x" +
                              std::to_string(L.d.NZ()) + (sizeof(T) == 4 ? "|f32" : "|f64");
     int v = 0;
-    const bool have_gs = cache.get(arch + "|gs|" + dims, v);
+    const bool have_gs = cache.get(arch + "|gsf|" + dims, v);
     if (have_gs) L.by_gs = v;
     const bool have_res = cache.get(arch + "|res|" + dims, v);
     if (have_res) L.by_res = v;
@@ -687,8 +689,8 @@ void autotune_levels(mcw_handle& h) {
     for (int which = 0; which < 2; ++which) {
       if ((which == 0 && have_gs) || (which == 1 && have_res)) continue;
       float best = 1e30f;
-      int best_by = 4;
-      for (int by : cand) {
+      int best_by = which == 0 ? 0 : 4;
+      for (int by : which == 0 ? cand_gs : cand_res) {
         auto run = [&] {
           if (which == 0) launch_smooth_sweep<T>(L.d, h.faces, st, L.f.as<T>(), L.x.as<T>(), h.stream, by);
           else
@@ -709,12 +711,13 @@ void autotune_levels(mcw_handle& h) {
       }
       if (which == 0) {
         L.by_gs = best_by;
-        cache.put(arch + "|gs|" + dims, best_by);
+        cache.put(arch + "|gsf|" + dims, best_by);
       } else {
         L.by_res = best_by;
         cache.put(arch + "|res|" + dims, best_by);
       }
-      logf(h, "autotune %s %s: %d rows per block", which == 0 ? "gs" : "res", dims.c_str(), best_by);
+      logf(h, "autotune %s %s: %d rows per block (0: fused rows)", which == 0 ? "gs" : "res", dims.c_str(),
+           best_by);
     }
   }
   cache.save();
@@ -1051,7 +1054,7 @@ class Batch {
         mcw_handle& h = *hs_[i];
         if (d + 1 < (int)h.levels.size() && h.levels[d].d.N() > big) {
           big = h.levels[d].d.N();
-          by_gs_[d] = h.levels[d].by_gs;
+          by_gs_[d] = std::max(1, h.levels[d].by_gs);  // batched passes are per colour
           by_res_[d] = h.levels[d].by_res;
         }
       }

@@ -209,10 +209,10 @@ def test_autotuned_tile_shapes_are_cached_and_do_not_change_results(tmp_path, mo
     g1, u0 = mcwind.grid_from_problem(p, autotune=True)
     g2, _ = mcwind.grid_from_problem(p, autotune=False)
     shapes = [g1.tile_rows(l) for l in range(g1.num_levels())]
-    assert all(s in (1, 2, 4) for pair in shapes for s in pair)
-    assert g2.tile_rows(0) == (4, 4)
+    assert all(p[0] in (0, 1, 2, 4) and p[1] in (1, 2, 4) for p in shapes)
+    assert g2.tile_rows(0) == (0, 4)
     text = cache.read_text()
-    assert "|gs|161x121x9|f32" in text and "|res|161x121x9|f32" in text
+    assert "|gsf|161x121x9|f32" in text and "|res|161x121x9|f32" in text
     g3, _ = mcwind.grid_from_problem(p, autotune=True)
     assert [g3.tile_rows(l) for l in range(g3.num_levels())] == shapes
     a, ua, _ = g1.solve(u0)
@@ -228,7 +228,7 @@ def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precisi
     mcwind = _mcw()
     cache = tmp_path / "tune.json"
     tag = "f64" if precision == "fp64" else "f32"
-    cache.write_text('{\n  "gfx950|gs|601x601x3|%s": 1,\n  "gfx950|res|601x601x3|%s": 1\n}\n'
+    cache.write_text('{\n  "gfx950|gsf|601x601x3|%s": 1,\n  "gfx950|res|601x601x3|%s": 1\n}\n'
                      % (tag, tag))
     monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
     p = inputs.hills_problem(600, 600, 2, 4, 8, a=(1.0, 1.0, 2.0))
@@ -241,3 +241,34 @@ def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precisi
                                      autotune=False)
     lam2, _, _ = g2.solve(u0, want_u=False)
     assert float((lam - lam2).abs().max() / lam2.abs().max()) < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp32_refine", "fp64"])
+def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision):
+    """The fused two-colour pass (one block per row) and the four separate colour
+    passes give the same sweep bit for bit, forward and reverse."""
+    mcwind = _mcw()
+    p = inputs.hills_problem(160, 120, 8, 4, 5, a=(1.0, 1.0, 2.0))
+    tag = "f32" if precision == "fp32_refine" else "f64"
+    grids = []
+    for shape in (0, 4):
+        cache = tmp_path / f"tune{shape}.json"
+        cache.write_text('{\n  "gfx950|gsf|161x121x9|%s": %d,\n  "gfx950|res|161x121x9|%s": 4\n}\n'
+                         % (tag, shape, tag))
+        monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
+        g, u0 = mcwind.grid_from_problem(p, precision=precision, krylov=True)
+        assert g.tile_rows(0)[0] == shape
+        grids.append(g)
+    dt = torch.float32 if precision == "fp32_refine" else torch.float64
+    rng = np.random.default_rng(3)
+    x0 = torch.from_numpy(rng.standard_normal((9, 121, 161))).to("cuda", dt)
+    f = torch.from_numpy(rng.standard_normal((9, 121, 161))).to("cuda", dt)
+    out = []
+    for g in grids:
+        x = x0.clone()
+        g.smooth(0, x, f, sweeps=2)
+        g.smooth(0, x, f, sweeps=-1)
+        lam, _, _ = g.solve(u0, want_u=False)
+        out.append((x, lam))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
