@@ -27,7 +27,10 @@ CPU-baseline leg; never by the product path.
   grid is still too large, coarsen horizontally anyway.
 * Beyond the paper: the symmetric V-cycle (post-smoothing in the reverse
   order) and conjugate gradients preconditioned by it, the textbook method
-  (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1).
+  (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1); and the
+  vertical line smoother, the other reading of "vertical sweeps": block
+  Gauss-Seidel whose blocks are the free nodes of one column, solved exactly,
+  in the same colour order.
 """
 from __future__ import annotations
 
@@ -205,6 +208,37 @@ def gs_sweep_full(K_full, mask, dims, x, f, order=None, reverse=False):
     return x
 
 
+def column_blocks(nx, ny, nz, mask, colour):
+    """Free node numbers of each column of one colour class (i mod 2, j mod 2)."""
+    ci, cj = colour
+    cols = []
+    for j in range(cj, ny + 1, 2):
+        for i in range(ci, nx + 1, 2):
+            c = [fem.node_index(i, j, k, nx, ny) for k in range(nz + 1)]
+            c = [n for n in c if mask[n]]
+            if c:
+                cols.append(np.asarray(c, dtype=np.int64))
+    return cols
+
+
+def line_sweep_full(K_full, mask, dims, x, f, reverse=False):
+    """One vertical line Gauss-Seidel sweep on full-length vectors (not in the
+    paper; the reading of "vertical sweeps" as exact column solves): colour by
+    colour, every free column c of the colour solves its own block,
+    x_c += K_cc^{-1} (f - K x)_c.  Columns of one colour do not couple, so the
+    residual of a colour is taken once.  reverse=True runs the colours in the
+    opposite order (the adjoint sweep)."""
+    nx, ny, nz = dims
+    x = np.array(x, dtype=np.float64)
+    order = COLOURS[::-1] if reverse else COLOURS
+    K = K_full.tocsr()
+    for colour in order:
+        r = f - K @ x
+        for c in column_blocks(nx, ny, nz, mask, colour):
+            x[c] += np.linalg.solve(K[c][:, c].toarray(), r[c])
+    return x
+
+
 class Multigrid:
     """V-cycle on the free-node systems of a hierarchy (eqs. (6)-(7)).
 
@@ -212,10 +246,11 @@ class Multigrid:
     the paper): with nu_pre == nu_post the V-cycle from zero is then a
     symmetric positive definite operator B, usable as a CG preconditioner."""
 
-    def __init__(self, levels, nu_pre=2, nu_post=2, symmetric=False):
+    def __init__(self, levels, nu_pre=2, nu_post=2, symmetric=False, smoother="point"):
         self.levels = levels
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.symmetric = symmetric
+        self.smoother = smoother
         self._orders = []
         self._tri = []
         self._tri_rev = []
@@ -231,6 +266,13 @@ class Multigrid:
         self._coarse = np.linalg.cholesky(levels[-1].K.toarray())
 
     def smooth(self, l, x, f, reverse=False):
+        if self.smoother == "line":
+            L = self.levels[l]
+            xf = np.zeros(L.mask.size)
+            ff = np.zeros(L.mask.size)
+            xf[L.free] = x
+            ff[L.free] = f
+            return line_sweep_full(L.K_full, L.mask, L.dims, xf, ff, reverse)[L.free]
         order = self._orders[l][::-1] if reverse else self._orders[l]
         tri = self._tri_rev[l] if reverse else self._tri[l]
         r = f - self.levels[l].K @ x
