@@ -84,6 +84,15 @@ typedef enum {
   MCW_COARSEN_FULL = 2
 } mcw_coarsen_rule;
 
+typedef enum {
+  /* Sec. 3: pointwise Gauss-Seidel, each column from the bottom up, colours
+     (0,0),(1,0),(0,1),(1,1) */
+  MCW_SMOOTH_POINT = 0,
+  /* vertical line Gauss-Seidel: each column's free nodes solved together
+     (tridiagonal in the column), the neighbour columns held fixed, same colours */
+  MCW_SMOOTH_LINE = 1
+} mcw_smoother;
+
 /* Problem statement (Sec. 2): node coordinates, penalties, Gamma. */
 typedef struct {
   int32_t nx, ny, nz;     /* elements per direction; nx, ny >= 2, nz >= 1 */
@@ -112,6 +121,7 @@ typedef struct {
                                  post-smoothing sweeps run in reverse: colours 3..0, each
                                  column top-down), restarted at every refinement step;
                                  needs nu_pre == nu_post */
+  int32_t smoother;           /* mcw_smoother; default MCW_SMOOTH_POINT */
 } mcw_options;
 
 #define MCW_MAX_LEVELS 24

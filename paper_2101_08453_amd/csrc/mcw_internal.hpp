@@ -319,9 +319,11 @@ void launch_tile_batched(int mode, const WorkList& W, hipStream_t s);
 void launch_recover_batched(const WorkList& W, hipStream_t s);
 
 // Multigrid kernels (templated on the V-cycle precision)
+// line_buf: null for the point smoother; for the vertical line smoother a
+// level-sized scratch vector (the elimination coefficients)
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s, int by = 4, bool reverse = false);
+                         hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr);
 // preconditioned conjugate gradients; sc = device scalars {r.z, alpha, beta, r.r}
 void launch_cg_reset(double* sc, hipStream_t s);
 template <class T>

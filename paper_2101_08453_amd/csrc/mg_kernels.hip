@@ -163,14 +163,97 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
   }
 }
 
+// Vertical line Gauss-Seidel on one column (i, j) of the colour in J: the
+// column's free nodes are solved together with the neighbour columns (and the
+// column's fixed end nodes) held at their current values.  The column block is
+// tridiagonal in the couplings o = 4 (below), 13 (self), 22 (above); forward
+// elimination from the bottom leaves the modified upper coefficients in J.r
+// and the modified right-hand sides in x, back substitution from the top
+// finishes x.  The solve is exact in the column, so a reverse sweep differs
+// from a forward one only in the order of the colours.
+template <class T>
+__device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
+  const T* __restrict__ st = static_cast<const T*>(J.st);
+  const T* __restrict__ f = static_cast<const T*>(J.f);
+  T* __restrict__ x = static_cast<T*>(J.x);
+  T* __restrict__ cb = static_cast<T*>(J.r);
+  const int NX = J.NX, NY = J.NY, NZ = J.NZ;
+  if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) return;
+  const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
+  const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
+  const StLayout L = dev_layout(NX, NY);
+  const int NXe = (NX + 1) >> 1;
+  const int sm = sx(im, NXe), s0 = sx(i, NXe), sp = sx(ip, NXe);
+  const int cols[9] = {jm * NX + sm, jm * NX + s0, jm * NX + sp, j * NX + sm, j * NX + s0,
+                       j * NX + sp, jp * NX + sm, jp * NX + s0, jp * NX + sp};
+  const size_t plane = (size_t)NX * NY;
+  const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
+  if (kf > kl) return;
+  T xb[9], x0[9], xa[9];  // planes k-1, k, k+1
+  {
+    const int kb = kf > 0 ? kf - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      xb[q] = x[(size_t)kb * plane + cols[q]];
+      x0[q] = x[(size_t)kf * plane + cols[q]];
+    }
+  }
+  T cprev = T(0), dprev = T(0);
+  for (int k = kf; k <= kl; ++k) {
+    const int ka = k + 1 < NZ ? k + 1 : NZ - 1;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) xa[q] = x[(size_t)ka * plane + cols[q]];
+    T a[SW];
+    load_stencil_nt(st, L.node(i, j, k), a);
+    T s = load_nt(f + (size_t)k * plane + cols[4]);
+    const bool first = k == kf, last = k == kl;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      if (o == 13) continue;
+      // the couplings to the column's own free nodes stay on the left-hand side
+      if (o == 4 && !first) continue;
+      if (o == 22 && !last) continue;
+      const int dk = o / 9, q = o % 9;
+      const T xv = dk == 0 ? xb[q] : (dk == 1 ? x0[q] : xa[q]);
+      s -= a[o] * xv;
+    }
+    const T sub = first ? T(0) : a[4];
+    const T sup = last ? T(0) : a[22];
+    const T den = a[13] - sub * cprev;
+    const T c = sup / den;
+    const T d = (s - sub * dprev) / den;
+    cb[(size_t)k * plane + cols[4]] = c;
+    x[(size_t)k * plane + cols[4]] = d;
+    cprev = c;
+    dprev = d;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      xb[q] = x0[q];
+      x0[q] = xa[q];
+    }
+  }
+  T xnext = dprev;  // x at kl is its modified right-hand side
+  for (int k = kl - 1; k >= kf; --k) {
+    const size_t p = (size_t)k * plane + cols[4];
+    xnext = x[p] - cb[p] * xnext;
+    x[p] = xnext;
+  }
+}
+
+template <class T, bool REV, bool LINE>
+__device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j) {
+  if (LINE) line_column<T>(J, i, j);
+  else gs_column<T, REV>(J, i, j);
+}
+
 // One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
 // tiles of 64 x J.by columns per block.
-template <class T, bool REV = false>
+template <class T, bool REV = false, bool LINE = false>
 __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
   const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
   const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   if (ii >= J.ncx || jj >= J.ncy) return;
-  gs_column<T, REV>(J, 2 * ii + J.ci, 2 * jj + J.cj);
+  smooth_column<T, REV, LINE>(J, 2 * ii + J.ci, 2 * jj + J.cj);
 }
 
 // Two colour passes of the same rows in one launch: colour J0 then colour J1
@@ -179,21 +262,23 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
 // block barrier between the two halves keeps the order of the separate passes
 // and gives the same result bit for bit, while x of rows j-1, j, j+1 is
 // fetched once for both colours.
-template <class T, bool REV>
+template <class T, bool REV, bool LINE>
 __global__ __launch_bounds__(1024) void gs_fused_kernel(ColJob J0, ColJob J1) {
   const int j = 2 * (int)blockIdx.x + J0.cj;
-  for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x) gs_column<T, REV>(J0, 2 * ii + J0.ci, j);
+  for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
+    smooth_column<T, REV, LINE>(J0, 2 * ii + J0.ci, j);
   __syncthreads();
-  for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x) gs_column<T, REV>(J1, 2 * ii + J1.ci, j);
+  for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
+    smooth_column<T, REV, LINE>(J1, 2 * ii + J1.ci, j);
 }
 
-template <class T, bool REV>
+template <class T, bool REV, bool LINE>
 __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
-  gs_pass_body<T, REV>(J, xcd_remap(blockIdx.x, J.nblocks));
+  gs_pass_body<T, REV, LINE>(J, xcd_remap(blockIdx.x, J.nblocks));
 }
 
 template <class T>
-__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false>(J, b); }
+__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false>(J, b); }
 
 template <class T>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
@@ -345,19 +430,20 @@ __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
   const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZf);
   const int xa = sx(X.mx.lo[i], NXec), xb = sx(X.mx.hi[i], NXec);
   const int ya = X.my.lo[j], yb = X.my.hi[j];
-  const T wx = X.mx.lo[i] == X.mx.hi[i] ? T(1) : T(0.5), wxb = X.mx.lo[i] == X.mx.hi[i] ? T(0) : T(0.5);
-  const T wy = ya == yb ? T(1) : T(0.5), wyb = ya == yb ? T(0) : T(0.5);
   const int NXc = X.NXc;
+  // a kept index reads one coarse value, a dropped one the mean of two; the
+  // conditions are uniform over a wave (one half-row) or the whole launch
+  // (planes), so each node loads only the coarse values it weighs
+  auto row_val = [&](const T* row) { return xa == xb ? row[xa] : T(0.5) * (row[xa] + row[xb]); };
+  auto plane_val = [&](const T* p) {
+    const T va = row_val(p + (size_t)ya * NXc);
+    return ya == yb ? va : T(0.5) * (va + row_val(p + (size_t)yb * NXc));
+  };
   for (int k = kf; k <= kl; ++k) {
     const int za = X.mz.lo[k], zb = X.mz.hi[k];
-    const T wz = za == zb ? T(1) : T(0.5), wzb = za == zb ? T(0) : T(0.5);
-    const T* pa = e + (size_t)za * pc;
-    const T* pb = e + (size_t)zb * pc;
-    auto plane_val = [&](const T* p) {
-      return wy * (wx * p[(size_t)ya * NXc + xa] + wxb * p[(size_t)ya * NXc + xb]) +
-             wyb * (wx * p[(size_t)yb * NXc + xa] + wxb * p[(size_t)yb * NXc + xb]);
-    };
-    x[(size_t)k * pf + (size_t)j * X.NXf + q] += wz * plane_val(pa) + wzb * plane_val(pb);
+    const T va = plane_val(e + (size_t)za * pc);
+    const T v = za == zb ? va : T(0.5) * (va + plane_val(e + (size_t)zb * pc));
+    x[(size_t)k * pf + (size_t)j * X.NXf + q] += v;
   }
 }
 
@@ -671,36 +757,45 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 
 // ---------------------------------------------------------------- single launches
 
-template <class T>
-void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
-                         hipStream_t s, int by, bool reverse) {
+template <class T, bool LINE>
+void smooth_sweep_t(const Dims& d, const Faces& fc, const T* st, const T* f, T* x, T* cbuf,
+                    hipStream_t s, int by, bool reverse) {
   if (by == 0) {
     // colours (0,0),(1,0) then (0,1),(1,1); reversed: (1,1),(0,1) then (1,0),(0,0)
     for (int pr = 0; pr < 2; ++pr) {
       const int c0 = reverse ? 3 - 2 * pr : 2 * pr, c1 = reverse ? c0 - 1 : c0 + 1;
-      const ColJob J0 = col_job(d, fc, st, f, x, nullptr, c0, 1);
-      const ColJob J1 = col_job(d, fc, st, f, x, nullptr, c1, 1);
+      const ColJob J0 = col_job(d, fc, st, f, x, cbuf, c0, 1);
+      const ColJob J1 = col_job(d, fc, st, f, x, cbuf, c1, 1);
       if (J0.ncy <= 0) continue;
       const int cols = std::max(J0.ncx, J1.ncx);
       const int threads = std::min(1024, std::max(64, (cols + 63) / 64 * 64));
       if (reverse)
-        gs_fused_kernel<T, true><<<J0.ncy, threads, 0, s>>>(J0, J1);
+        gs_fused_kernel<T, true, LINE><<<J0.ncy, threads, 0, s>>>(J0, J1);
       else
-        gs_fused_kernel<T, false><<<J0.ncy, threads, 0, s>>>(J0, J1);
+        gs_fused_kernel<T, false, LINE><<<J0.ncy, threads, 0, s>>>(J0, J1);
       MCW_CHECK_LAUNCH();
     }
     return;
   }
   for (int cc = 0; cc < 4; ++cc) {
     const int c = reverse ? 3 - cc : cc;
-    const ColJob J = col_job(d, fc, st, f, x, nullptr, c, by);
+    const ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
     if (J.nblocks <= 0) continue;
     if (reverse)
-      gs_pass_kernel<T, true><<<J.nblocks, BX * by, 0, s>>>(J);
+      gs_pass_kernel<T, true, LINE><<<J.nblocks, BX * by, 0, s>>>(J);
     else
-      gs_pass_kernel<T, false><<<J.nblocks, BX * by, 0, s>>>(J);
+      gs_pass_kernel<T, false, LINE><<<J.nblocks, BX * by, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
+}
+
+template <class T>
+void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
+                         hipStream_t s, int by, bool reverse, T* line_buf) {
+  if (line_buf)
+    smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse);
+  else
+    smooth_sweep_t<T, false>(d, fc, st, f, x, nullptr, s, by, reverse);
 }
 
 // ---- conjugate gradients on level-0 vectors, coefficients kept on the device
@@ -1036,7 +1131,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 
 #define MCW_INST(T)                                                                             \
   template void launch_smooth_sweep<T>(const Dims&, const Faces&, const T*, const T*, T*,       \
-                                       hipStream_t, int, bool);                                 \
+                                       hipStream_t, int, bool, T*);                             \
   template void launch_cg_beta<T>(const T*, const T*, const T*, size_t, double*, size_t,       \
                                   double*, hipStream_t);                                        \
   template void launch_add<T>(T*, const T*, size_t, hipStream_t);                              \

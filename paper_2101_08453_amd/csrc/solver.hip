@@ -302,6 +302,13 @@ template <class T> const T* stencil_of(const Level& L);
 template <> const double* stencil_of<double>(const Level& L) { return L.st64.as<double>(); }
 template <> const float* stencil_of<float>(const Level& L) { return L.st32.as<float>(); }
 
+// Scratch of the vertical line smoother (the level's residual vector, idle
+// while smoothing), or null for the point smoother.
+template <class T>
+T* line_buf(const mcw_handle& h, Level& L) {
+  return h.opt.smoother == MCW_SMOOTH_LINE ? L.r.as<T>() : nullptr;
+}
+
 template <class T>
 void vcycle(mcw_handle& h, int l, T* x, const T* f) {
   Level& L = h.levels[l];
@@ -311,7 +318,8 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
     return;
   }
   const T* st = stencil_of<T>(L);
-  for (int s = 0; s < h.opt.nu_pre; ++s) launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs);
+  for (int s = 0; s < h.opt.nu_pre; ++s)
+    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L));
   launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res);
   Level& C = h.levels[l + 1];
   launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
@@ -320,7 +328,7 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
   launch_prolong_dims<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, C.x.as<T>(), x, h.stream);
   // with krylov the post-smoother is the adjoint of the pre-smoother, so the cycle is symmetric
   for (int s = 0; s < h.opt.nu_post; ++s)
-    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, h.opt.krylov != 0);
+    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, h.opt.krylov != 0, line_buf<T>(h, L));
 }
 
 // Run `record` on h.stream, or, with use_graph, replay the hipGraph it was
@@ -678,7 +686,8 @@ void autotune_levels(mcw_handle& h) {
     const std::string dims = std::to_string(L.d.NX()) + "x" + std::to_string(L.d.NY()) + "x" +
                              std::to_string(L.d.NZ()) + (sizeof(T) == 4 ? "|f32" : "|f64");
     int v = 0;
-    const bool have_gs = cache.get(arch + "|gsf|" + dims, v);
+    const std::string gs_key = arch + (h.opt.smoother == MCW_SMOOTH_LINE ? "|gsl|" : "|gsf|") + dims;
+    const bool have_gs = cache.get(gs_key, v);
     if (have_gs) L.by_gs = v;
     const bool have_res = cache.get(arch + "|res|" + dims, v);
     if (have_res) L.by_res = v;
@@ -692,7 +701,9 @@ void autotune_levels(mcw_handle& h) {
       int best_by = which == 0 ? 0 : 4;
       for (int by : which == 0 ? cand_gs : cand_res) {
         auto run = [&] {
-          if (which == 0) launch_smooth_sweep<T>(L.d, h.faces, st, L.f.as<T>(), L.x.as<T>(), h.stream, by);
+          if (which == 0)
+            launch_smooth_sweep<T>(L.d, h.faces, st, L.f.as<T>(), L.x.as<T>(), h.stream, by, false,
+                                   line_buf<T>(h, L));
           else
             launch_residual<T>(L.d, h.faces, st, L.x.as<T>(), L.f.as<T>(), L.r.as<T>(), nullptr, nullptr,
                                h.stream, by);
@@ -711,7 +722,7 @@ void autotune_levels(mcw_handle& h) {
       }
       if (which == 0) {
         L.by_gs = best_by;
-        cache.put(arch + "|gsf|" + dims, best_by);
+        cache.put(gs_key, best_by);
       } else {
         L.by_res = best_by;
         cache.put(arch + "|res|" + dims, best_by);
@@ -742,6 +753,7 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
   if (o.coarse_direct_max < 1 || o.coarse_direct_max > 4096) Fail::arg("coarse_direct_max must be in [1, 4096]");
   if (o.krylov != 0 && o.krylov != 1) Fail::arg("krylov must be 0 or 1");
   if (o.krylov && o.nu_pre != o.nu_post) Fail::arg("krylov needs nu_pre == nu_post (a symmetric V-cycle)");
+  if (o.smoother != MCW_SMOOTH_POINT && o.smoother != MCW_SMOOTH_LINE) Fail::arg("bad smoother");
 }
 
 void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, mcw_handle& h) {
@@ -955,7 +967,7 @@ void smooth_t(mcw_handle& h, int l, T* x, const T* f, int sweeps) {
   const bool reverse = sweeps < 0;
   for (int s = 0; s < std::abs(sweeps); ++s)
     launch_smooth_sweep<T>(L.d, h.faces, stencil_of<T>(L), L.f.as<T>(), L.x.as<T>(), h.stream,
-                           L.by_gs, reverse);
+                           L.by_gs, reverse, line_buf<T>(h, L));
   launch_relayout<T>(L.d, L.x.as<T>(), x, false, h.stream);
 }
 
@@ -1464,10 +1476,11 @@ mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) Fail::arg("a handle appears twice in the batch");
   }
-  bool any_krylov = false;
-  for (int i = 0; i < m; ++i) any_krylov = any_krylov || hs[i]->opt.krylov;
-  if (hs[0]->opt.precision != MCW_FP32_REFINE || any_krylov) {
-    // plain FP64 and CG handles are solved one after another
+  bool sequential = false;
+  for (int i = 0; i < m; ++i)
+    sequential = sequential || hs[i]->opt.krylov || hs[i]->opt.smoother != MCW_SMOOTH_POINT;
+  if (hs[0]->opt.precision != MCW_FP32_REFINE || sequential) {
+    // plain FP64, CG and line-smoother handles are solved one after another
     mcw_status first = MCW_OK;
     for (int i = 0; i < m; ++i) {
       const mcw_status s = solve_impl(*hs[i], u0[i], lambda[i], u ? u[i] : nullptr,
@@ -1501,6 +1514,7 @@ void mcw_default_options(mcw_options* o) {
   o->verbose = std::getenv("MCW_LOG") ? 1 : 0;
   o->autotune = 1;
   o->krylov = 0;
+  o->smoother = MCW_SMOOTH_POINT;
 }
 
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
@@ -1807,7 +1821,8 @@ mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps
       if (is_f32(h)) {
         float *x = L.x.as<float>(), *f = L.f.as<float>(), *rr = L.r.as<float>();
         if (kernel == 0)
-          launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), f, x, h->stream, L.by_gs);
+          launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), f, x, h->stream, L.by_gs, false,
+                                     line_buf<float>(*h, L));
         if (kernel == 1)
           launch_residual<float>(L.d, h->faces, L.st32.as<float>(), x, f, rr, nullptr, nullptr, h->stream,
                                  L.by_res);
@@ -1822,7 +1837,8 @@ mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps
       } else {
         double *x = L.x.as<double>(), *f = L.f.as<double>(), *rr = L.r.as<double>();
         if (kernel == 0)
-          launch_smooth_sweep<double>(L.d, h->faces, L.st64.as<double>(), f, x, h->stream, L.by_gs);
+          launch_smooth_sweep<double>(L.d, h->faces, L.st64.as<double>(), f, x, h->stream, L.by_gs, false,
+                                      line_buf<double>(*h, L));
         if (kernel == 1)
           launch_residual<double>(L.d, h->faces, L.st64.as<double>(), x, f, rr, nullptr, nullptr, h->stream,
                                   L.by_res);

@@ -28,6 +28,7 @@ FP64 = 0
 FP32_REFINE = 1
 PRECISIONS = {"fp64": FP64, "fp32_refine": FP32_REFINE}
 RULES = {"operator": 0, "literal": 1, "full": 2}
+SMOOTHERS = {"point": 0, "line": 1}
 MAX_LEVELS = 24
 HISTORY = 64
 
@@ -47,7 +48,7 @@ class Options(ctypes.Structure):
                 ("coarsen_rule", ctypes.c_int32), ("coarse_direct_max", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("autotune", ctypes.c_int32),
-                ("krylov", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -166,7 +167,7 @@ class Grid:
     def __init__(self, X, Y, Z, a, gamma=GAMMA_BOTTOM, precision="fp32_refine", rtol=1e-8,
                  max_cycles=200, nu_pre=2, nu_post=2, inner_cycles=0, coarsen_rule="operator",
                  coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True,
-                 krylov=False):
+                 krylov=False, smoother="point"):
         L = lib()
         self._h = H()
         nzp, nyp, nxp = X.shape
@@ -194,6 +195,7 @@ class Grid:
         o.use_graph = 1 if use_graph else 0
         o.autotune = 1 if autotune else 0
         o.krylov = 1 if krylov else 0
+        o.smoother = SMOOTHERS[smoother]
         o.verbose = 1 if (verbose or os.environ.get("MCW_LOG")) else 0
         self.precision = precision
         self.vdtype = torch.float32 if precision == "fp32_refine" else torch.float64

@@ -243,20 +243,22 @@ def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precisi
     assert float((lam - lam2).abs().max() / lam2.abs().max()) < 1e-8
 
 
+@pytest.mark.parametrize("smoother", ["point", "line"])
 @pytest.mark.parametrize("precision", ["fp32_refine", "fp64"])
-def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision):
+def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision, smoother):
     """The fused two-colour pass (one block per row) and the four separate colour
     passes give the same sweep bit for bit, forward and reverse."""
     mcwind = _mcw()
     p = inputs.hills_problem(160, 120, 8, 4, 5, a=(1.0, 1.0, 2.0))
     tag = "f32" if precision == "fp32_refine" else "f64"
+    key = "gsf" if smoother == "point" else "gsl"
     grids = []
     for shape in (0, 4):
         cache = tmp_path / f"tune{shape}.json"
-        cache.write_text('{\n  "gfx950|gsf|161x121x9|%s": %d,\n  "gfx950|res|161x121x9|%s": 4\n}\n'
-                         % (tag, shape, tag))
+        cache.write_text('{\n  "gfx950|%s|161x121x9|%s": %d,\n  "gfx950|res|161x121x9|%s": 4\n}\n'
+                         % (key, tag, shape, tag))
         monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
-        g, u0 = mcwind.grid_from_problem(p, precision=precision, krylov=True)
+        g, u0 = mcwind.grid_from_problem(p, precision=precision, krylov=True, smoother=smoother)
         assert g.tile_rows(0)[0] == shape
         grids.append(g)
     dt = torch.float32 if precision == "fp32_refine" else torch.float64
