@@ -241,7 +241,8 @@ def bench_rules(args):
     operator-consistent and the printed ratio) on 512x512x15 fractal terrain
     with the slopes of the 3000x3000 grid, for a3 in {1, 2, 5, 10} and layer
     stretching 1.0 / 1.2: V-cycles and rate to 1e-8 (plain FP64, cold start),
-    by the multigrid iteration and by multigrid-preconditioned CG."""
+    by the multigrid iteration and by multigrid-preconditioned CG, with the
+    point smoother and (operator and full rules) the vertical line smoother."""
     import torch
 
     from paper_2101_08453_amd import inputs, mcwind
@@ -256,22 +257,26 @@ def bench_rules(args):
             u0 = inputs._log_wind(n, n, nz, zeta, 8.0, 0.3)
             p = inputs.Problem("rules", X, Y, Z, u0, np.array([1.0, 1.0, a3]))
             for rule in ("operator", "literal", "full"):
-                for krylov in (False, True):
-                    g, u0t = mcwind.grid_from_problem(p, precision="fp64", coarsen_rule=rule,
-                                                      max_cycles=400, krylov=krylov)
-                    g.solve(u0t, check=False, want_u=False)  # warm-up (graph capture)
-                    lam, _, info = g.solve(u0t, check=False)
-                    lv = [L["dims"] for L in g.levels()]
-                    work = sum((d[0] + 1) * (d[1] + 1) * (d[2] + 1) for d in lv) / p.n_nodes
-                    rows.append({"stretch": ratio, "a3": a3, "rule": rule,
-                                 "method": "mg-pcg" if krylov else "multigrid",
-                                 "cycles": info["cycles"], "rho": round(info["rho"], 3),
-                                 "status": info["status"], "levels": len(lv),
-                                 "grid_work": round(work, 3), "ms": round(info["ms_total"], 1)})
-                    log(rows[-1])
-                    g.close()
-                    del u0t
-                    torch.cuda.empty_cache()
+                for smoother in ("point", "line"):
+                    if rule == "literal" and smoother == "line":
+                        continue
+                    for krylov in (False, True):
+                        g, u0t = mcwind.grid_from_problem(p, precision="fp64", coarsen_rule=rule,
+                                                          max_cycles=400, krylov=krylov,
+                                                          smoother=smoother)
+                        g.solve(u0t, check=False, want_u=False)  # warm-up (graph capture)
+                        lam, _, info = g.solve(u0t, check=False)
+                        lv = [L["dims"] for L in g.levels()]
+                        work = sum((d[0] + 1) * (d[1] + 1) * (d[2] + 1) for d in lv) / p.n_nodes
+                        rows.append({"stretch": ratio, "a3": a3, "rule": rule, "smoother": smoother,
+                                     "method": "mg-pcg" if krylov else "multigrid",
+                                     "cycles": info["cycles"], "rho": round(info["rho"], 3),
+                                     "status": info["status"], "levels": len(lv),
+                                     "grid_work": round(work, 3), "ms": round(info["ms_total"], 1)})
+                        log(rows[-1])
+                        g.close()
+                        del u0t
+                        torch.cuda.empty_cache()
     print(json.dumps({"workload": "coarsening rules, 512x512x15", "rows": rows}), flush=True)
 
 
