@@ -27,9 +27,9 @@ def _loss(u, mask_t):
     return (u[0, 0][mask_t] ** 2).sum() + (u[1, 0][mask_t] ** 2).sum()
 
 
-def _grad_gpu(p, mask, rtol=1e-12):
+def _grad_gpu(p, mask, rtol=1e-12, **kw):
     mcwind = _mcw()
-    g, u0 = mcwind.grid_from_problem(p, rtol=rtol)
+    g, u0 = mcwind.grid_from_problem(p, rtol=rtol, **kw)
     u0 = u0.clone().requires_grad_(True)
     a = torch.tensor(p.a, dtype=torch.float64, device="cuda", requires_grad=True)
     u = mcwind.WindSolve.apply(u0, a, g)
@@ -53,6 +53,19 @@ def test_gradient_matches_oracle():
     L_ref, g_u0_ref, g_a_ref = oadj.gradient(p, mask)
     assert abs(L - L_ref) <= 1e-10 * abs(L_ref)
     # dL/du0 is returned in FP32
+    assert np.abs(g_u0 - g_u0_ref).max() <= 1e-5 * np.abs(g_u0_ref).max()
+    assert np.allclose(g_a, g_a_ref, rtol=1e-8, atol=1e-10 * np.abs(g_a_ref).max())
+
+
+@pytest.mark.parametrize("kw", [dict(krylov=True), dict(smoother="line"),
+                                dict(precision="fp64", krylov=True, smoother="line")])
+def test_gradient_with_solver_variants_matches_oracle(kw):
+    """The transpose solve runs through the handle's own solver: CG, the line
+    smoother and plain FP64 give the same gradient."""
+    p, mask = _small()
+    _, L, g_u0, g_a = _grad_gpu(p, mask, **kw)
+    L_ref, g_u0_ref, g_a_ref = oadj.gradient(p, mask)
+    assert abs(L - L_ref) <= 1e-10 * abs(L_ref)
     assert np.abs(g_u0 - g_u0_ref).max() <= 1e-5 * np.abs(g_u0_ref).max()
     assert np.allclose(g_a, g_a_ref, rtol=1e-8, atol=1e-10 * np.abs(g_a_ref).max())
 

@@ -274,3 +274,40 @@ def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, pr
         out.append((x, lam))
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])
+
+
+def test_3000x3000x15_warm_solve_sampled_against_oracle():
+    """The benchmark's configuration: 3000x3000x15, a = (1,1,10), FP32 V-cycles in
+    FP64 refinement, warm started from the previous step's lambda after the wind
+    is perturbed, to relative residual 1e-8.  The oracle recomputes f - K lambda
+    of the GPU's lambda on windows (corner, interior, edge) and the recovered
+    wind on a window; the weak divergence equals the residual at any size."""
+    mcwind = _mcw()
+    p = inputs.c3()
+    du = inputs.c3_perturbation(p.u0.shape)
+    print("[case] 3000x3000x15 warm solve", flush=True)
+    dev = torch.device("cuda")
+    g = mcwind.Grid(*(torch.from_numpy(A).to(dev) for A in (p.X, p.Y, p.Z)), p.a, rtol=1e-10)
+    u0 = torch.from_numpy(p.u0).to(dev)
+    lam, _, _ = g.solve(u0, want_u=False)
+    g.set_tolerance(1e-8)
+    q = inputs.Problem("perturbed", p.X, p.Y, p.Z, p.u0 + du, p.a, p.gamma)
+    u0p = torch.from_numpy(q.u0).to(dev)
+    lam, u, info = g.solve(u0p, lam=lam)
+    assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-8
+    assert abs(info["rel_divergence"] - info["rel_residual"]) <= 1e-6 * info["rel_residual"]
+    r_dev = g.rhs(u0p) - g.apply_K(lam)
+    m = torch.from_numpy(fem.free_mask(*p.dims, p.gamma)).to(dev)
+    r_dev = torch.where(m, r_dev, torch.zeros_like(r_dev))
+    assert abs(float(r_dev.norm()) / info["f_norm"] - info["rel_residual"]) < 1e-3 * info["rel_residual"]
+    del m
+    lam_h = lam.cpu().numpy()
+    for (i0, i1, j0, j1) in [(0, 20, 0, 20), (1490, 1512, 1480, 1500), (2985, 3001, 10, 30)]:
+        r_or, _ = _window_residual(q, lam_h, i0, i1, j0, j1)
+        sub = r_dev[:, j0:j1, i0:i1].cpu().numpy()
+        assert np.abs(r_or - sub).max() <= 1e-10 * info["f_norm"]
+    u_h = u[:, :, 1000:1030, 2000:2030].cpu().numpy()
+    lw = lam_h[:, 1000:1031, 2000:2031]
+    Xw, Yw, Zw = (A[:, 1000:1031, 2000:2031] for A in (p.X, p.Y, p.Z))
+    u_ref = fem.recover(Xw, Yw, Zw, q.u0[:, :, 1000:1030, 2000:2030], p.a, lw)
+    assert gc.rel_err(u_h, u_ref) < 1e-12
