@@ -138,6 +138,18 @@ def test_linear_lambda_gradient_exact_on_distorted_mesh():
         assert np.abs(g[d] - alpha[d]).max() < 1e-12
 
 
+def test_recovery_of_a_linear_multiplier():
+    """Trilinear elements reproduce a linear lambda, so its centre gradient is
+    exactly (alpha, beta, gamma) even on a distorted mesh, and eq. (3) fixes the
+    recovered wind: u = u0 + A^-1 (alpha, beta, gamma) with A^-1 = diag(a_d^-2)."""
+    p = inputs.distorted_problem(5, 4, 3, seed=11, amp=0.25, a=(0.5, 2.0, 4.0))
+    g = np.array([0.7, -1.3, 2.1])
+    lam = g[0] * p.X + g[1] * p.Y + g[2] * p.Z
+    u = fem.recover(p.X, p.Y, p.Z, p.u0, p.a, lam)
+    ref = p.u0 + (g / np.asarray(p.a) ** 2)[:, None, None, None]
+    assert np.abs(u - ref).max() < 1e-12 * np.abs(ref).max()
+
+
 def test_volumes_of_box_grid():
     X, Y, Z = _box_grid(3.0, 2.0, 1.0, 3, 2, 2, zeta=np.array([0.0, 1.0, 2.5]))
     v = fem.element_volumes(X, Y, Z)
