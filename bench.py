@@ -205,6 +205,35 @@ def bench_c4(args):
             g.close()
         del g32
         torch.cuda.empty_cache()
+        # the same ensemble with CG preconditioned by the symmetric V-cycle
+        gk = [mcwind.grid_from_problem(p, krylov=True)[0] for p in probs]
+        lk = [g._node() for g in gk]
+
+        def batch_cg():
+            for l in lk:
+                l.zero_()
+            return mcwind.solve_batch(gk, u0s, lams=lk)
+
+        batch_cg()
+        e0.record(stream)
+        for _ in range(args.steps):
+            _, _, infk, stk = batch_cg()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_batch_cg = e0.elapsed_time(e1) / args.steps
+        cyk = [i["cycles"] for i in infk]
+        sequential(gk)
+        e0.record(stream)
+        sequential(gk)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_seq_cg = e0.elapsed_time(e1)
+        log(f"batched mg-pcg: {ms_batch_cg:.1f} ms, steps {min(cyk)}..{max(cyk)}, {stk}; "
+            f"sequential mg-pcg {ms_seq_cg:.1f} ms")
+        for g in gk:
+            g.close()
+        del gk
+        torch.cuda.empty_cache()
         t0 = time.perf_counter()
         g64 = [mcwind.Grid(torch.from_numpy(p.X).to(dev), torch.from_numpy(p.Y).to(dev),
                            torch.from_numpy(p.Z).to(dev), p.a, precision="fp64") for p in probs]
@@ -232,6 +261,9 @@ def bench_c4(args):
                                    "ms": round(ms_seq32, 2), "setup_s": round(setup32, 2)},
         "max_lambda_rel_diff_vs_fp64": err,
         "cycles": [min(cyc), max(cyc)],
+        "batched_mg_pcg": {"value": round(nodes / ms_batch_cg / 1e3, 2), "ms": round(ms_batch_cg, 2),
+                           "steps": [min(cyk), max(cyk)]},
+        "sequential_mg_pcg": {"value": round(nodes / ms_seq_cg / 1e3, 2), "ms": round(ms_seq_cg, 2)},
     }
     print(json.dumps(out), flush=True)
 

@@ -158,6 +158,7 @@ struct ColJob {  // smoother colour pass, residual
   int ci, cj, ncx, ncy;  // colour class and its column counts (smoother)
   int by;                // rows of 64-column tiles per block (block = 64 * by threads)
   int tiles_x, nblocks;  // local grid of 64 x by column tiles
+  double* part;          // per-block partial sums of a batched residual with a dot product
 };
 
 struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
@@ -224,6 +225,20 @@ struct RecoverJob {  // u = u0 + diag(c) grad lambda at element centres
 
 // Work list of a batched launch: job j owns global blocks [prefix[j], prefix[j+1]);
 // member[j] indexes the per-member active flags.
+struct CgJob {  // conjugate-gradient vectors of one batch member (level 0, row-split order)
+  void* e;           // correction
+  void* p;           // direction
+  const void* z;     // preconditioned residual
+  void* r;           // residual
+  const void* q;     // -K p
+  double* sc;        // 4 device scalars {r.z, alpha, beta, r.r}
+  double* partials;  // the member's partial-sum buffer
+  size_t n;          // vector length
+  int nblocks;       // blocks of the vector kernels, cg_blocks(n)
+  int res_blocks;    // blocks of the member's q = -K p launch
+  int member;
+};
+
 struct WorkList {
   const void* jobs;
   const int* prefix;
@@ -382,7 +397,15 @@ CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, vo
 VecJob vec_job(void* p, const void* q, size_t n, const double* scale);
 
 // Batched (persistent) launches over a work list of jobs
-template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by = 4);
+template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by = 4, bool reverse = false);
+// batched conjugate gradients (lists of CgJob; residual lists of ColJob with part set)
+unsigned cg_blocks(size_t n);
+template <class T> void launch_dot2_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_cg_direction_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_cg_update_batched(const WorkList& W, hipStream_t s);
+template <class T> void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by);
+void launch_cg_coeff_batched(const CgJob* jobs, int n, int mode, const int* active, hipStream_t s);
+void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStream_t s);
 template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by = 4);
 template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);

@@ -279,10 +279,17 @@ __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
 
 template <class T>
 __device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false>(J, b); }
+template <class T>
+__device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false>(J, b); }
 
 template <class T>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
   MCW_BATCHED_LOOP(ColJob, gs_pass_fwd<T>)
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gs_pass_batched_rev(WorkList W) {
+  MCW_BATCHED_LOOP(ColJob, gs_pass_rev<T>)
 }
 
 // ---------------------------------------------------------------- residual
@@ -363,6 +370,21 @@ __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restr
 
 template <class T>
 __device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T>(J, b); }
+
+// q = -K p with p.q per block, as residual_kernel<T, true, true> does for block b
+template <class T>
+__device__ __forceinline__ void residual_dot_item(const ColJob& J, int b) {
+  __shared__ double s_red[256];
+  const double acc = residual_body<T, true>(J, xcd_remap(b, J.nblocks));
+  if (threadIdx.x == 0)
+    for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
+  block_sum_to(acc, s_red, &J.part[b]);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void residual_dot_batched(WorkList W) {
+  MCW_BATCHED_LOOP(ColJob, residual_dot_item<T>)
+}
 
 template <class T>
 __global__ __launch_bounds__(256) void residual_batched(WorkList W) {
@@ -799,32 +821,46 @@ void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f
 }
 
 // ---- conjugate gradients on level-0 vectors, coefficients kept on the device
-// sc[0] = r.z of the current step, sc[1] = alpha, sc[2] = beta.
+// sc[0] = r.z of the current step, sc[1] = alpha, sc[2] = beta, sc[3] = r.r.
+// Each kernel is a body run by block `blk` of `nblk` (grid-stride within the
+// vector), so a batched launch over several members does the same arithmetic,
+// in the same order, as the single launch of each.
 
 namespace {
 
 // per-block FP64 partial sums of a.b and, when c is given, a.c (channel-major)
 template <class T>
-__global__ __launch_bounds__(256) void dot2_kernel(const T* __restrict__ a, const T* __restrict__ b,
-                                                   const T* __restrict__ c, size_t n,
-                                                   double* __restrict__ partials) {
-  __shared__ double s_red[256];
+__device__ __forceinline__ void dot2_body(const T* __restrict__ a, const T* __restrict__ b,
+                                          const T* __restrict__ c, size_t n,
+                                          double* __restrict__ partials, int blk, int nblk,
+                                          double* s_red) {
   double ab = 0.0, ac = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+  for (size_t i = (size_t)blk * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256) {
     const double av = a[i];
     ab += av * (double)b[i];
     if (c) ac += av * (double)c[i];
   }
-  block_sum_to(ab, s_red, &partials[blockIdx.x]);
-  if (c) block_sum_to(ac, s_red, &partials[gridDim.x + blockIdx.x]);
+  block_sum_to(ab, s_red, &partials[blk]);
+  if (c) block_sum_to(ac, s_red, &partials[nblk + blk]);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void dot2_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                   const T* __restrict__ c, size_t n,
+                                                   double* __restrict__ partials) {
+  __shared__ double s_red[256];
+  dot2_body<T>(a, b, c, n, partials, blockIdx.x, gridDim.x, s_red);
+}
+
+__device__ __forceinline__ void cg_reset_body(double* sc) {
+  sc[0] = 1.0;
+  sc[1] = 0.0;
+  sc[2] = 0.0;
+  sc[3] = 0.0;
 }
 
 __global__ void cg_reset_kernel(double* sc) {
-  if (threadIdx.x == 0) {
-    sc[0] = 1.0;
-    sc[1] = 0.0;
-    sc[2] = 0.0;
-  }
+  if (threadIdx.x == 0) cg_reset_body(sc);
 }
 
 // mode 0: the partials hold z.r and z.q of the new preconditioned residual z,
@@ -833,10 +869,8 @@ __global__ void cg_reset_kernel(double* sc) {
 //   that is symmetric only up to rounding; zero on the first step (alpha = 0).
 // mode 1: the partials hold p.q = -p.Kp; alpha = (r.z) / p.Kp, zero on breakdown.
 // mode 2: the partials hold r.r after the update; sc[3] = r.r.
-__global__ __launch_bounds__(256) void cg_coeff_kernel(const double* __restrict__ partials,
-                                                       size_t n_part, int mode, double* sc) {
-  __shared__ double s[256];
-  __shared__ double tot[2];
+__device__ __forceinline__ void cg_coeff_body(const double* __restrict__ partials, size_t n_part,
+                                              int mode, double* sc, double* s, double* tot) {
   sum_body(SumJob{partials, n_part, mode == 0 ? 2 : 1, tot}, s);
   if (threadIdx.x == 0) {
     if (mode == 0) {
@@ -850,33 +884,110 @@ __global__ __launch_bounds__(256) void cg_coeff_kernel(const double* __restrict_
       sc[3] = tot[0];
     }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void cg_coeff_kernel(const double* __restrict__ partials,
+                                                       size_t n_part, int mode, double* sc) {
+  __shared__ double s[256];
+  __shared__ double tot[2];
+  cg_coeff_body(partials, n_part, mode, sc, s, tot);
 }
 
 // p = z + beta p (p = z on the first step, so p need not start finite)
 template <class T>
-__global__ __launch_bounds__(256) void cg_direction_kernel(T* __restrict__ p, const T* __restrict__ z,
-                                                           const double* __restrict__ sc, size_t n) {
+__device__ __forceinline__ void cg_direction_body(T* __restrict__ p, const T* __restrict__ z,
+                                                  const double* __restrict__ sc, size_t n, int blk,
+                                                  int nblk) {
   const T beta = (T)sc[2];
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+  for (size_t i = (size_t)blk * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256)
     p[i] = beta == T(0) ? z[i] : z[i] + beta * p[i];
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void cg_direction_kernel(T* __restrict__ p, const T* __restrict__ z,
+                                                           const double* __restrict__ sc, size_t n) {
+  cg_direction_body<T>(p, z, sc, n, blockIdx.x, gridDim.x);
+}
+
 // e += alpha p; r += alpha q (q = -K p), with per-block partial sums of the new r.r
+template <class T>
+__device__ __forceinline__ void cg_update_body(T* __restrict__ e, const T* __restrict__ p,
+                                               T* __restrict__ r, const T* __restrict__ q,
+                                               const double* __restrict__ sc, size_t n,
+                                               double* __restrict__ partials, int blk, int nblk,
+                                               double* s_red) {
+  const T alpha = (T)sc[1];
+  double rr = 0.0;
+  for (size_t i = (size_t)blk * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256) {
+    e[i] += alpha * p[i];
+    const T rn = r[i] + alpha * q[i];
+    r[i] = rn;
+    rr += (double)rn * (double)rn;
+  }
+  block_sum_to(rr, s_red, &partials[blk]);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void cg_update_kernel(T* __restrict__ e, const T* __restrict__ p,
                                                         T* __restrict__ r, const T* __restrict__ q,
                                                         const double* __restrict__ sc, size_t n,
                                                         double* __restrict__ partials) {
   __shared__ double s_red[256];
-  const T alpha = (T)sc[1];
-  double rr = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    e[i] += alpha * p[i];
-    const T rn = r[i] + alpha * q[i];
-    r[i] = rn;
-    rr += (double)rn * (double)rn;
+  cg_update_body<T>(e, p, r, q, sc, n, partials, blockIdx.x, gridDim.x, s_red);
+}
+
+// ---- batched forms: one work item is one block of one member's vector
+
+template <class T>
+__device__ __forceinline__ void dot2_item(const CgJob& C, int b) {
+  __shared__ double s_red[256];
+  dot2_body<T>(static_cast<const T*>(C.z), static_cast<const T*>(C.r), static_cast<const T*>(C.q), C.n,
+               C.partials, b, C.nblocks, s_red);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void dot2_batched(WorkList W) {
+  MCW_BATCHED_LOOP(CgJob, dot2_item<T>)
+}
+
+template <class T>
+__device__ __forceinline__ void direction_item(const CgJob& C, int b) {
+  cg_direction_body<T>(static_cast<T*>(C.p), static_cast<const T*>(C.z), C.sc, C.n, b, C.nblocks);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void cg_direction_batched(WorkList W) {
+  MCW_BATCHED_LOOP(CgJob, direction_item<T>)
+}
+
+template <class T>
+__device__ __forceinline__ void update_item(const CgJob& C, int b) {
+  __shared__ double s_red[256];
+  cg_update_body<T>(static_cast<T*>(C.e), static_cast<const T*>(C.p), static_cast<T*>(C.r),
+                    static_cast<const T*>(C.q), C.sc, C.n, C.partials, b, C.nblocks, s_red);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void cg_update_batched(WorkList W) {
+  MCW_BATCHED_LOOP(CgJob, update_item<T>)
+}
+
+// one block per member; members whose flag is off keep their coefficients
+__global__ __launch_bounds__(256) void cg_coeff_batched(const CgJob* __restrict__ jobs, int n, int mode,
+                                                        const int* __restrict__ active) {
+  __shared__ double s[256];
+  __shared__ double tot[2];
+  for (int j = blockIdx.x; j < n; j += gridDim.x) {
+    if (!active[jobs[j].member]) continue;
+    const size_t np = mode == 1 ? (size_t)jobs[j].res_blocks : (size_t)jobs[j].nblocks;
+    cg_coeff_body(jobs[j].partials, np, mode, jobs[j].sc, s, tot);
   }
-  block_sum_to(rr, s_red, &partials[blockIdx.x]);
+}
+
+__global__ void cg_reset_batched(const CgJob* __restrict__ jobs, int n, const int* __restrict__ active) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && active[jobs[j].member]) cg_reset_body(jobs[j].sc);
 }
 
 template <class T>
@@ -884,9 +995,9 @@ __global__ __launch_bounds__(256) void add_kernel(T* __restrict__ y, const T* __
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) y[i] += x[i];
 }
 
-unsigned dot_blocks(size_t n) { return std::min<unsigned>(grid_stride_blocks(n), 2048); }
-
 }  // namespace
+
+unsigned cg_blocks(size_t n) { return std::min<unsigned>(grid_stride_blocks(n), 2048); }
 
 void launch_cg_reset(double* sc, hipStream_t s) {
   cg_reset_kernel<<<1, 64, 0, s>>>(sc);
@@ -896,7 +1007,7 @@ void launch_cg_reset(double* sc, hipStream_t s) {
 template <class T>
 void launch_cg_beta(const T* z, const T* r, const T* q, size_t n, double* partials, size_t cap,
                     double* sc, hipStream_t s) {
-  const unsigned blocks = dot_blocks(n);
+  const unsigned blocks = cg_blocks(n);
   need_partials(2 * (size_t)blocks, cap);
   dot2_kernel<T><<<blocks, 256, 0, s>>>(z, r, q, n, partials);
   MCW_CHECK_LAUNCH();
@@ -924,7 +1035,7 @@ void launch_cg_direction(T* p, const T* z, const double* sc, size_t n, hipStream
 template <class T>
 void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, double* partials,
                       size_t cap, hipStream_t s) {
-  const unsigned blocks = dot_blocks(n);
+  const unsigned blocks = cg_blocks(n);
   need_partials(blocks, cap);
   cg_update_kernel<T><<<blocks, 256, 0, s>>>(e, p, r, q, sc, n, partials);
   MCW_CHECK_LAUNCH();
@@ -1064,9 +1175,52 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
 // ---------------------------------------------------------------- batched launches
 
 template <class T>
-void launch_gs_batched(const WorkList& W, hipStream_t s, int by) {
+void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse) {
   if (W.total <= 0) return;
-  gs_pass_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  if (reverse)
+    gs_pass_batched_rev<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  else
+    gs_pass_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_dot2_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  dot2_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_cg_direction_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  cg_direction_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_cg_update_batched(const WorkList& W, hipStream_t s) {
+  if (W.total <= 0) return;
+  cg_update_batched<T><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by) {
+  if (W.total <= 0) return;
+  residual_dot_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_cg_coeff_batched(const CgJob* jobs, int n, int mode, const int* active, hipStream_t s) {
+  if (n <= 0) return;
+  cg_coeff_batched<<<(unsigned)n, 256, 0, s>>>(jobs, n, mode, active);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStream_t s) {
+  if (n <= 0) return;
+  cg_reset_batched<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(jobs, n, active);
   MCW_CHECK_LAUNCH();
 }
 
@@ -1151,7 +1305,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_coarse_solve<T>(int, const double*, const int*, const T*, T*,            \
                                        hipStream_t);                                            \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
-  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int);                        \
+  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool);                  \
   template void launch_residual_batched<T>(const WorkList&, hipStream_t, int);                  \
   template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
   template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \
@@ -1159,6 +1313,11 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_fill_batched<T>(const WorkList&, hipStream_t);
 MCW_INST(float)
 MCW_INST(double)
+
+template void launch_dot2_batched<float>(const WorkList&, hipStream_t);
+template void launch_cg_direction_batched<float>(const WorkList&, hipStream_t);
+template void launch_cg_update_batched<float>(const WorkList&, hipStream_t);
+template void launch_neg_apply_dot_batched<float>(const WorkList&, hipStream_t, int);
 #undef MCW_INST
 
 }  // namespace mcw

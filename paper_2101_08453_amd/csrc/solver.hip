@@ -1040,10 +1040,13 @@ class Batch {
   Batch(std::vector<mcw_handle*> hs) : hs_(std::move(hs)), m_((int)hs_.size()), s_(hs_[0]->stream) {}
   ~Batch() {
     if (graph_) (void)hipGraphExecDestroy(graph_);
+    if (cg_graph_) (void)hipGraphExecDestroy(cg_graph_);
     if (host_sums_) (void)hipHostFree(host_sums_);
+    if (host_cg_) (void)hipHostFree(host_cg_);
   }
 
   void build() {
+    krylov_ = hs_[0]->opt.krylov != 0;
     depth_ = 0;
     for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
     gs_.assign(depth_, {});
@@ -1136,7 +1139,8 @@ class Batch {
       sc.push_back(vec_job(h.levels[0].f.p, h.r64.p, N, nullptr));
       sc.back().NX = h.d.NX();
       f0.push_back(vec_job(h.levels[0].x.p, nullptr, N, nullptr));
-      up.push_back(vec_job(nullptr, h.levels[0].x.p, N, nullptr));
+      // the correction: the V-cycles' x, or the CG solution e
+      up.push_back(vec_job(nullptr, krylov_ ? h.ke.p : h.levels[0].x.p, N, nullptr));
       up.back().NX = h.d.NX();
       s1.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 1, nullptr});
       s2.push_back(SumJob{h.partials.as<double>(), (size_t)A.gx * A.gy, 2, nullptr});
@@ -1164,9 +1168,53 @@ class Batch {
     s1_off_ = add_raw(s1.data(), s1.size() * sizeof(SumJob));
     s2_off_ = add_raw(s2.data(), s2.size() * sizeof(SumJob));
     active_off_ = add_raw(nullptr, m_ * sizeof(int));
+    if (krylov_) build_cg(all);
     blob_.alloc(host_.size());
     base_ = blob_.as<char>();
     MCW_HIP(hipHostMalloc((void**)&host_sums_, (size_t)m_ * 4 * sizeof(double), hipHostMallocDefault));
+    if (krylov_) {
+      // the coefficient slots live in the blob: point the jobs at them
+      for (int i = 0; i < m_; ++i) cg_jobs_[i].sc = dev<double>(cg_slot_) + 4 * i;
+      put(cgvec_, cg_jobs_);
+      std::memcpy(&host_[cgtab_off_], cg_jobs_.data(), cg_jobs_.size() * sizeof(CgJob));
+      MCW_HIP(hipHostMalloc((void**)&host_cg_, (size_t)m_ * 4 * sizeof(double), hipHostMallocDefault));
+    }
+  }
+
+  // Work lists of the batched conjugate gradients: the vector kernels over
+  // every member's level-0 vectors, q = -K p with p.q, and the fill of e.
+  void build_cg(const std::vector<int>& all) {
+    std::vector<ColJob> cr;
+    std::vector<VecJob> fe;
+    cg_jobs_.clear();
+    for (int i = 0; i < m_; ++i) {
+      mcw_handle& h = *hs_[i];
+      Level& V = h.levels[0];
+      const size_t N = V.d.N();
+      ColJob J = col_job(V.d, h.faces, V.st32.p, nullptr, h.kp.p, h.kq.p, -1, by_res_[0]);
+      J.part = h.partials.as<double>();
+      need_partials((size_t)J.nblocks, h.n_partials);
+      need_partials(2 * (size_t)cg_blocks(N), h.n_partials);
+      cr.push_back(J);
+      CgJob C{};
+      C.e = h.ke.p;
+      C.p = h.kp.p;
+      C.z = V.x.p;
+      C.r = V.f.p;
+      C.q = h.kq.p;
+      C.partials = h.partials.as<double>();
+      C.n = N;
+      C.nblocks = (int)cg_blocks(N);
+      C.res_blocks = J.nblocks;
+      C.member = i;
+      cg_jobs_.push_back(C);
+      fe.push_back(vec_job(h.ke.p, nullptr, N, nullptr));
+    }
+    cg_slot_ = alloc_host((size_t)m_ * 4 * sizeof(double));
+    cgvec_ = add(cg_jobs_, all);
+    cgres_ = add(cr, all);
+    cgfill_ = add(fe, all);
+    cgtab_off_ = add_raw(cg_jobs_.data(), cg_jobs_.size() * sizeof(CgJob));
   }
 
   // Solve all members; returns the first non-OK member status.
@@ -1226,6 +1274,8 @@ class Batch {
     }
     MCW_HIP(hipEventRecord(h0.ev[1], s_));
     const double tol = h0.opt.rtol;
+    std::vector<double> cg_stop2(m_, 0.0);
+    std::vector<int> cg_mmax(m_, 0);
     for (;;) {
       set_active(act);
       upload_active();
@@ -1263,8 +1313,12 @@ class Batch {
         mi = std::min(mi, h.opt.max_cycles - S.cycles);
         want = std::max(want, mi);
         const double nfree = (double)std::max<size_t>(free_count(h.d, h.faces), 1);
-        reinterpret_cast<double*>(&host_[scales_slot_])[i] =
-            std::ldexp(1.0, -std::ilogb(std::sqrt(rr / nfree)));
+        const double scale = std::ldexp(1.0, -std::ilogb(std::sqrt(rr / nfree)));
+        reinterpret_cast<double*>(&host_[scales_slot_])[i] = scale;
+        // CG stops on its own residual: the same target, in the scaled FP32 units
+        cg_mmax[i] = std::min(h.opt.inner_cycles > 0 ? h.opt.inner_cycles : 30, h.opt.max_cycles - S.cycles);
+        const double stop = h.opt.inner_cycles > 0 ? 0.0 : std::max(tol / S.rel, 3e-5) * std::sqrt(rr) * scale;
+        cg_stop2[i] = stop * stop;
       }
       for (int i = 0; i < m_; ++i) act[i] = ms[i].active ? 1 : 0;
       if (want == 0) break;
@@ -1273,13 +1327,18 @@ class Batch {
                              hipMemcpyHostToDevice, s_));
       upload_active();
       launch_scale_batched(fix(sc_), s_);
-      launch_fill_batched<float>(fix(f0_), s_);
-      for (int c = 0; c < want; ++c) vcycle();
+      std::vector<int> took(m_, want);
+      if (krylov_) {
+        took = cg_inner(act, cg_stop2, cg_mmax);
+      } else {
+        launch_fill_batched<float>(fix(f0_), s_);
+        for (int c = 0; c < want; ++c) vcycle();
+      }
       launch_update_batched(fix(up_), s_);
       for (int i = 0; i < m_; ++i)
         if (ms[i].active) {
-          ms[i].cycles += want;
-          ms[i].prev_m = want;
+          ms[i].cycles += took[i];
+          ms[i].prev_m = took[i];
           ms[i].prev_rel = ms[i].rel;
         }
       MCW_HIP(hipStreamSynchronize(s_));  // host_ staging is rewritten next step
@@ -1362,6 +1421,7 @@ class Batch {
   static int nblocks_of(const VecJob& V) { return V.nblocks; }
   static int nblocks_of(const TileJob& A) { return A.gx * A.gy; }
   static int nblocks_of(const RecoverJob& R) { return R.gx * R.gy; }
+  static int nblocks_of(const CgJob& C) { return C.nblocks; }
 
   size_t add_raw(const void* p, size_t bytes) {
     const size_t off = (host_.size() + 255) & ~size_t(255);
@@ -1416,8 +1476,85 @@ class Batch {
     launch_fill_batched<float>(fix(fillx_[d]), s_);
     if (d + 1 < depth_) vcycle_levels(d + 1);
     launch_prolong_batched<float>(fix(prol_[d]), s_);
+    // with CG the post-smoother is the reverse sweep, which keeps the cycle symmetric
     for (int s = 0; s < nu_post; ++s)
-      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d]);
+      for (int cc = 0; cc < 4; ++cc) {
+        const int c = krylov_ ? 3 - cc : cc;
+        launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d], krylov_);
+      }
+  }
+
+  // One batched CG step for the members whose flag is on (the single-handle
+  // step of pcg_step, member by member in one launch per phase).
+  void cg_step_record() {
+    const int* act = dev<int>(active_off_);
+    const CgJob* tab = dev<CgJob>(cgtab_off_);
+    launch_fill_batched<float>(fix(f0_), s_);  // z = 0
+    vcycle_levels(0);
+    launch_dot2_batched<float>(fix(cgvec_), s_);
+    launch_cg_coeff_batched(tab, m_, 0, act, s_);
+    launch_cg_direction_batched<float>(fix(cgvec_), s_);
+    launch_neg_apply_dot_batched<float>(fix(cgres_), s_, by_res_[0]);
+    launch_cg_coeff_batched(tab, m_, 1, act, s_);
+    launch_cg_update_batched<float>(fix(cgvec_), s_);
+    launch_cg_coeff_batched(tab, m_, 2, act, s_);
+  }
+
+  void cg_step() {
+    if (!hs_[0]->opt.use_graph) {
+      cg_step_record();
+      return;
+    }
+    if (!cg_graph_) {
+      hipGraph_t g = nullptr;
+      MCW_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      try {
+        cg_step_record();
+      } catch (...) {
+        (void)hipStreamEndCapture(s_, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      MCW_HIP(hipStreamEndCapture(s_, &g));
+      const hipError_t e = hipGraphInstantiate(&cg_graph_, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      MCW_HIP(e);
+    }
+    MCW_HIP(hipGraphLaunch(cg_graph_, s_));
+  }
+
+  // CG from e = 0 for the members in `act` until each one's recursive r.r
+  // falls to its stop2 (0: never) or it has taken its mmax steps; returns the
+  // steps of each member.  Leaves the flags of `act` set again.
+  std::vector<int> cg_inner(const std::vector<int>& act, const std::vector<double>& stop2,
+                            const std::vector<int>& mmax) {
+    std::vector<int> a = act, steps(m_, 0);
+    set_active(a);
+    upload_active();
+    launch_cg_reset_batched(dev<CgJob>(cgtab_off_), m_, dev<int>(active_off_), s_);
+    launch_fill_batched<float>(fix(cgfill_), s_);
+    for (int i = 0; i < m_; ++i)
+      if (a[i] && mmax[i] <= 0) a[i] = 0;
+    for (;;) {
+      bool any = false;
+      for (int i = 0; i < m_; ++i) any = any || a[i];
+      if (!any) break;
+      set_active(a);
+      upload_active();
+      cg_step();
+      MCW_HIP(hipMemcpyAsync(host_cg_, base_ + cg_slot_, (size_t)m_ * 4 * sizeof(double),
+                             hipMemcpyDeviceToHost, s_));
+      MCW_HIP(hipStreamSynchronize(s_));
+      for (int i = 0; i < m_; ++i) {
+        if (!a[i]) continue;
+        ++steps[i];
+        const double rr = host_cg_[4 * i + 3];
+        if (steps[i] >= mmax[i] || (stop2[i] > 0.0 && !(rr > stop2[i]))) a[i] = 0;
+      }
+    }
+    set_active(act);
+    upload_active();
+    return steps;
   }
 
   void vcycle() {
@@ -1446,6 +1583,12 @@ class Batch {
   std::vector<mcw_handle*> hs_;
   int m_;
   hipStream_t s_;
+  bool krylov_ = false;
+  hipGraphExec_t cg_graph_ = nullptr;
+  double* host_cg_ = nullptr;
+  std::vector<CgJob> cg_jobs_;
+  WorkList cgvec_{}, cgres_{}, cgfill_{};
+  size_t cg_slot_ = 0, cgtab_off_ = 0;
   int depth_ = 0, max_coarse_ = 0;
   std::vector<std::array<WorkList, 4>> gs_;
   std::vector<int> by_gs_, by_res_;
@@ -1478,9 +1621,11 @@ mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u
   }
   bool sequential = false;
   for (int i = 0; i < m; ++i)
-    sequential = sequential || hs[i]->opt.krylov || hs[i]->opt.smoother != MCW_SMOOTH_POINT;
+    sequential = sequential || hs[i]->opt.krylov != hs[0]->opt.krylov ||
+                 hs[i]->opt.smoother != MCW_SMOOTH_POINT;
   if (hs[0]->opt.precision != MCW_FP32_REFINE || sequential) {
-    // plain FP64, CG and line-smoother handles are solved one after another
+    // plain FP64, line-smoother handles and batches mixing CG with the plain
+    // iteration are solved one after another
     mcw_status first = MCW_OK;
     for (int i = 0; i < m; ++i) {
       const mcw_status s = solve_impl(*hs[i], u0[i], lambda[i], u ? u[i] : nullptr,

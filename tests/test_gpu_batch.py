@@ -86,3 +86,50 @@ def test_batch_of_ensemble_members_against_fp64_solves():
         print(f"[c4] {p.name}: cycles {info['cycles']} rel err vs fp64 {err:.2e}")
         assert err < 1e-5
         g64.close()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_cg_matches_oracle_and_single_cg(use_graph):
+    """Members of uneven sizes and depths advanced together by batched CG (one
+    symmetric V-cycle per step); each member stops on its own residual."""
+    mcwind = _mcw()
+    probs = _members()
+    print(f"[case] batched CG of {len(probs)} use_graph={use_graph}", flush=True)
+    grids, u0s = zip(*[mcwind.grid_from_problem(p, rtol=1e-12, krylov=True, use_graph=use_graph)
+                       for p in probs])
+    lams, us, infos, status = mcwind.solve_batch(list(grids), list(u0s))
+    assert status == "MCW_OK"
+    for p, g, u0, lam, u, info in zip(probs, grids, u0s, lams, us, infos):
+        lam_ref, u_ref, _ = osolve.solve(p, rtol=1e-14)
+        assert info["rel_residual"] <= 1e-12
+        assert gc.rel_err(lam.cpu().numpy(), lam_ref) < 1e-8
+        assert gc.rel_err(u.cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8
+        lam1, _, info1 = g.solve(u0.clone(), want_u=False)
+        assert float((lam - lam1).abs().max() / lam1.abs().max()) < 1e-9
+        print(f"[cg] {p.name}: batched {info['cycles']} steps, single {info1['cycles']}", flush=True)
+
+
+def test_batched_cg_isolates_a_non_finite_member():
+    mcwind = _mcw()
+    probs = _members()[:2]
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p, krylov=True) for p in probs])]
+    gn, un = mcwind.grid_from_problem(inputs.hills_problem(20, 20, 6, 2, 9), krylov=True)
+    un[0, 1, 2, 3] = float("inf")
+    lams, us, infos, status = mcwind.solve_batch(grids + [gn], u0s + [un], check=False)
+    assert status == "MCW_NONFINITE"
+    for i in range(2):
+        assert infos[i]["rel_residual"] <= 1e-8
+        lam1, _, _ = grids[i].solve(u0s[i].clone(), want_u=False)
+        assert float((lams[i] - lam1).abs().max() / lam1.abs().max()) < 1e-6
+
+
+def test_batch_mixing_cg_and_multigrid_runs_one_after_another():
+    mcwind = _mcw()
+    probs = _members()[:2]
+    g0, u0 = mcwind.grid_from_problem(probs[0], krylov=True)
+    g1, u1 = mcwind.grid_from_problem(probs[1], krylov=False)
+    lams, _, infos, status = mcwind.solve_batch([g0, g1], [u0, u1])
+    assert status == "MCW_OK"
+    for g, u, lam in ((g0, u0, lams[0]), (g1, u1, lams[1])):
+        lam1, _, _ = g.solve(u.clone(), want_u=False)
+        assert torch.equal(lam, lam1)
