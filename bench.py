@@ -123,6 +123,16 @@ def kernel_table(g, stream, n_free):
     # coordinates (24 B), lambda, f and r (8 B each) per node; FP64 VALU bound
     b = 48.0 * N
     out["apply_K_matfree_f64"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
+    # a plain device copy of 2 GiB (read + write), the bandwidth a simple
+    # streaming kernel reaches on this GPU
+    import torch
+    src = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = time_on_stream(stream, lambda: dst.copy_(src), 4)
+    b = 2.0 * src.numel() * 4
+    out["device_copy"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
+    del src, dst
     return out
 
 
@@ -477,6 +487,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counted_traffic(),
+                "copy_GB/s": round(kernels["device_copy"]["GB/s"], 1),
+                "frac_of_copy": round(achieved / kernels["device_copy"]["GB/s"], 4),
                 "kernel": ("gs_fused_kernel<float, false> (fine-grid colour passes, two per launch)"
                            if k["launches_per_sweep"] == 2 else
                            "gs_pass_kernel<float, false> (fine-grid colour pass)"),

@@ -394,7 +394,10 @@ __global__ __launch_bounds__(256) void residual_batched(WorkList W) {
 // ---------------------------------------------------------------- transfers
 
 // rc = P^T r: coarse node (I,J,K) gathers the fine nodes of its support with
-// weight 1 (the kept node) or 1/2 (a dropped neighbour), per direction.
+// weight 1 (the kept node) or 1/2 (a dropped neighbour), per direction.  A
+// thread marches up one coarse column: each fine plane's horizontal sum is
+// formed once and shared by the (at most two) coarse planes whose support
+// holds it.
 template <class T>
 __device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
   const T* __restrict__ r = static_cast<const T*>(X.src);
@@ -408,18 +411,28 @@ __device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
   const int xlo = X.mx.slo[I], xhi = X.mx.shi[I], xc = X.mx.ctr[I];
   const int ylo = X.my.slo[J], yhi = X.my.shi[J], yc = X.my.ctr[J];
   const int NXef = (X.NXf + 1) >> 1, NXec = (X.NXc + 1) >> 1;
+  // horizontal part of P^T on fine plane pz
+  auto plane_sum = [&](int pz) {
+    T h = T(0);
+    for (int py = ylo; py <= yhi; ++py) {
+      const T* row = r + (size_t)pz * pf + (size_t)py * X.NXf;
+      T v = T(0);
+      for (int px = xlo; px <= xhi; ++px) v += (px == xc ? T(1) : T(0.5)) * row[sx(px, NXef)];
+      h += (py == yc ? T(1) : T(0.5)) * v;
+    }
+    return h;
+  };
+  int last_pz = -1;
+  T last_h = T(0);
   for (int K = 0; K < X.NZc; ++K) {
     T v = T(0);
     if (colfree && K >= kf && K <= kl) {
       const int zlo = X.mz.slo[K], zhi = X.mz.shi[K], zc = X.mz.ctr[K];
       for (int pz = zlo; pz <= zhi; ++pz) {
-        const T wz = pz == zc ? T(1) : T(0.5);
-        for (int py = ylo; py <= yhi; ++py) {
-          const T wy = py == yc ? wz : T(0.5) * wz;
-          const T* row = r + (size_t)pz * pf + (size_t)py * X.NXf;
-          for (int px = xlo; px <= xhi; ++px)
-            v += (px == xc ? wy : T(0.5) * wy) * row[sx(px, NXef)];
-        }
+        const T h = pz == last_pz ? last_h : plane_sum(pz);
+        last_pz = pz;
+        last_h = h;
+        v += (pz == zc ? T(1) : T(0.5)) * h;
       }
     }
     rc[(size_t)K * pc + (size_t)J * X.NXc + sx(I, NXec)] = v;
@@ -461,10 +474,23 @@ __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
     const T va = row_val(p + (size_t)ya * NXc);
     return ya == yb ? va : T(0.5) * (va + row_val(p + (size_t)yb * NXc));
   };
+  // consecutive fine planes share coarse planes: keep the last two values
+  int c0 = -1, c1 = -1;
+  T v0 = T(0), v1 = T(0);
+  auto coarse_plane = [&](int z) {
+    if (z == c1) return v1;
+    if (z == c0) return v0;
+    const T v = plane_val(e + (size_t)z * pc);
+    c0 = c1;
+    v0 = v1;
+    c1 = z;
+    v1 = v;
+    return v;
+  };
   for (int k = kf; k <= kl; ++k) {
     const int za = X.mz.lo[k], zb = X.mz.hi[k];
-    const T va = plane_val(e + (size_t)za * pc);
-    const T v = za == zb ? va : T(0.5) * (va + plane_val(e + (size_t)zb * pc));
+    const T va = coarse_plane(za);
+    const T v = za == zb ? va : T(0.5) * (va + coarse_plane(zb));
     x[(size_t)k * pf + (size_t)j * X.NXf + q] += v;
   }
 }
