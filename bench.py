@@ -52,7 +52,7 @@ def parse():
                     help="skip the multigrid-preconditioned CG comparison")
     ap.add_argument("--no-coupling", action="store_true",
                     help="skip timing the steps around the solve")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules", "configs"],
                     help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
                          "rules: coarsening rules across penalties and layer stretching")
     ap.add_argument("--members", type=int, default=64)
@@ -278,6 +278,55 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_configs(args):
+    """The configurations the oracle finishes on the host in a minute or two
+    (32x32x8 Gaussian hill, 256x256x16 with 40 hills): GPU solves in both
+    precisions and the oracle's cold Jacobi-PCG solve, each to relative
+    residual 1e-8 from lambda = 0, with the error of the GPU's lambda against
+    the oracle's."""
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    from oracle import solve as osolve
+    from paper_2101_08453_amd import inputs, mcwind
+    rows = []
+    for name, make in (("32x32x8 gaussian hill", inputs.c1), ("256x256x16 40 hills", inputs.c2)):
+        p = make()
+        row = {"config": name, "nodes": p.n_nodes}
+        for prec in ("fp32_refine", "fp64"):
+            g, u0 = mcwind.grid_from_problem(p, precision=prec, rtol=1e-8)
+            lam = g._node()
+            g.solve(u0, lam=lam)  # warm-up (graph capture, caches)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record()
+            for _ in range(reps):
+                lam.zero_()
+                _, _, info = g.solve(u0, lam=lam)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[prec] = {"ms": round(ms, 3), "Mnodes/s": round(p.n_nodes / ms / 1e3, 2),
+                         "cycles": info["cycles"], "rel_residual": info["rel_residual"]}
+            row[prec + "_lambda"] = lam.cpu().numpy()
+            g.close()
+        log(f"{name}: GPU done, oracle running")
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            lam_o, _, oinfo = osolve.solve(p, method="cg", rtol=1e-8)
+            t = time.perf_counter() - t0
+        row["oracle"] = {"s": round(t, 2), "Mnodes/s": round(p.n_nodes / t / 1e6, 4), "cores": 1,
+                         "iterations": oinfo["iterations"], "method": oinfo["method"]}
+        for prec in ("fp32_refine", "fp64"):
+            lg = row.pop(prec + "_lambda")
+            row[prec]["lambda_rel_diff_vs_oracle"] = float(np.abs(lg - lam_o).max() / np.abs(lam_o).max())
+        log(row)
+        rows.append(row)
+    print(json.dumps({"workload": "oracle-sized configurations", "host_cpus": os.cpu_count(),
+                      "rows": rows}), flush=True)
+
+
 def bench_rules(args):
     """Base method (full 2x2x2 coarsening) against adaptive semicoarsening (the
     operator-consistent and the printed ratio) on 512x512x15 fractal terrain
@@ -344,6 +393,9 @@ def main():
         return
     if args.workload == "rules":
         bench_rules(args)
+        return
+    if args.workload == "configs":
+        bench_configs(args)
         return
 
     from paper_2101_08453_amd import inputs, mcwind
