@@ -95,7 +95,8 @@ typedef enum {
 
 /* Problem statement (Sec. 2): node coordinates, penalties, Gamma. */
 typedef struct {
-  int32_t nx, ny, nz;     /* elements per direction; nx, ny >= 2, nz >= 1 */
+  int32_t nx, ny, nz;     /* elements per direction; nx, ny >= 2, nz >= 1; ny <= 262140,
+                             nz <= 4096, (nx+1)(ny+1) <= 2^30 */
   const double* X;        /* device, N node x-coordinates (copied by mcw_create) */
   const double* Y;        /* device, N node y-coordinates */
   const double* Z;        /* device, N node z-coordinates */

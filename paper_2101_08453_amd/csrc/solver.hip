@@ -742,6 +742,8 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
   if (g->nx < 2 || g->ny < 2 || g->nz < 1) Fail::arg("need nx >= 2, ny >= 2, nz >= 1");
   if ((long long)(g->nx + 1) * (g->ny + 1) > (1LL << 30) || g->nz > 4096)
     Fail::arg("grid too large");
+  // element-column kernels launch ceil(ny / 4) blocks along y
+  if (g->ny > 4 * 65535) Fail::arg("ny must be at most 262140");
   for (int d = 0; d < 3; ++d)
     if (!(g->a[d] > 0.0) || !std::isfinite(g->a[d])) Fail::arg("penalty constants must be finite and > 0");
   if (g->gamma_faces > 63u) Fail::arg("gamma_faces has bits beyond the six faces");
