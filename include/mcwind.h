@@ -144,6 +144,7 @@ typedef struct {
   float ms_cycles;                /* V-cycles (incl. casts/updates) */
   float ms_outer;                 /* FP64 matrix-free residuals */
   float ms_finish;                /* recovery and divergence check */
+  int32_t status;                 /* mcw_status of this solve; for a batch, the member's own */
 } mcw_info;
 
 typedef struct mcw_handle mcw_handle;

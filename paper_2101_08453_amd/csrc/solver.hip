@@ -613,6 +613,7 @@ mcw_status solve_impl(mcw_handle& h, const double* u0, double* lam, double* u, m
     MCW_HIP(hipEventElapsedTime(&t, h.ev[0], h.ev[1])); info->ms_rhs = t;
     MCW_HIP(hipEventElapsedTime(&t, h.ev[1], h.ev[2])); info->ms_cycles = t - pg.ms_outer;
     MCW_HIP(hipEventElapsedTime(&t, h.ev[2], h.ev[3])); info->ms_finish = t;
+    info->status = st;
   }
   return st;
 }
@@ -1390,6 +1391,7 @@ class Batch {
       info->ms_rhs = t_rhs;
       info->ms_cycles = t_iter;
       info->ms_finish = t_fin;
+      info->status = S.st;
     }
     return first;
   }
@@ -1737,7 +1739,13 @@ mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, f
     Progress pg;
     mcw_status st = MCW_OK;
     if (gnorm > 0.0) st = iterate(*h, mu, gnorm, pg);
-    if (st != MCW_OK && st != MCW_NOT_CONVERGED) return st;
+    if (st != MCW_OK && st != MCW_NOT_CONVERGED) {
+      if (info) {
+        fill_info(*h, pg, info);
+        info->status = st;
+      }
+      return st;
+    }
     double dc[3] = {0.0, 0.0, 0.0};
     launch_adjoint_elements(*h, g_u, lambda, mu, dL_du0, h->partials.as<double>(), &np);
     reduce_to_host(*h, np, 3, dc);
@@ -1745,6 +1753,7 @@ mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, f
     if (info) {
       fill_info(*h, pg, info);
       info->f_norm = gnorm;
+      info->status = st;
     }
     return st;
   });

@@ -59,7 +59,7 @@ class Info(ctypes.Structure):
                 ("n_history", ctypes.c_int32), ("history", ctypes.c_double * HISTORY),
                 ("ms_total", ctypes.c_float), ("ms_rhs", ctypes.c_float),
                 ("ms_cycles", ctypes.c_float), ("ms_outer", ctypes.c_float),
-                ("ms_finish", ctypes.c_float)]
+                ("ms_finish", ctypes.c_float), ("status", ctypes.c_int32)]
 
     def to_dict(self):
         return {
@@ -70,6 +70,7 @@ class Info(ctypes.Structure):
             "history": [self.history[i] for i in range(self.n_history)],
             "ms_total": self.ms_total, "ms_rhs": self.ms_rhs, "ms_cycles": self.ms_cycles,
             "ms_outer": self.ms_outer, "ms_finish": self.ms_finish,
+            "status": STATUS_NAMES[self.status] if 0 <= self.status < len(STATUS_NAMES) else str(self.status),
         }
 
 

@@ -60,6 +60,7 @@ def test_batch_equals_single_solves_and_isolates_failures():
     un[1, 2, 3, 4] = float("nan")
     lams, us, infos, status = mcwind.solve_batch(grids + [gz, gn], u0s + [uz, un], check=False)
     assert status == "MCW_NONFINITE"
+    assert [i["status"] for i in infos] == ["MCW_OK"] * 4 + ["MCW_NONFINITE"]
     for i, g in enumerate(grids):
         lam1, _, _ = g.solve(u0s[i].clone())
         assert infos[i]["rel_residual"] <= 1e-8
@@ -117,6 +118,7 @@ def test_batched_cg_isolates_a_non_finite_member():
     un[0, 1, 2, 3] = float("inf")
     lams, us, infos, status = mcwind.solve_batch(grids + [gn], u0s + [un], check=False)
     assert status == "MCW_NONFINITE"
+    assert [i["status"] for i in infos] == ["MCW_OK", "MCW_OK", "MCW_NONFINITE"]
     for i in range(2):
         assert infos[i]["rel_residual"] <= 1e-8
         lam1, _, _ = grids[i].solve(u0s[i].clone(), want_u=False)
