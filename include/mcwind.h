@@ -183,8 +183,12 @@ mcw_status mcw_solve(mcw_handle* h, const double* u0, double* lambda, double* u,
  * its own handle, advancing them together: every multigrid phase is one
  * launch over all members that still iterate.  Arrays as in mcw_solve, one
  * per member (host arrays of device pointers); infos may be NULL or hold m
- * entries.  All handles must share one device and precision; the stream of
- * hs[0] is used.  Returns the first non-OK member status. */
+ * entries, each with the member's own status.  All handles must share one
+ * device, precision and smoothing counts; the stream of hs[0] is used.
+ * FP32_REFINE members with krylov = 1 run batched CG, each member stopping
+ * on its own residual; FP64 handles, line-smoother handles and batches that
+ * mix CG with the plain iteration are solved one member after another.
+ * Returns the first non-OK member status. */
 mcw_status mcw_solve_batch(int32_t m, mcw_handle* const* hs, const double* const* u0,
                            double* const* lambda, double* const* u, mcw_info* infos);
 
