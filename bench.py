@@ -52,6 +52,7 @@ def parse():
                     help="skip the multigrid-preconditioned CG comparison")
     ap.add_argument("--no-coupling", action="store_true",
                     help="skip timing the steps around the solve")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules", "configs"],
                     help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
                          "rules: coarsening rules across penalties and layer stretching")
@@ -457,6 +458,32 @@ def main():
             kernels = kernel_table(g, stream, n_free)
             for k, v in kernels.items():
                 log(f"kernel {k}: {v['ms']:.3f} ms, {v['GB/s']:.0f} GB/s")
+        adjoint = None
+        if not args.no_adjoint:
+            # gradient of the surface-wind loss over a fire perimeter: the transpose
+            # multigrid solve (cold) plus the adjoints of recovery and right-hand side
+            lam_a = lam_prev.clone()
+            _, u_a, _ = g.solve(u0p, lam=lam_a)
+            mask = torch.from_numpy(inputs.fire_mask(n, n)).to(dev)
+            g_u = torch.zeros_like(u_a)
+            g_u[0, 0][mask] = 2.0 * u_a[0, 0][mask]
+            g_u[1, 0][mask] = 2.0 * u_a[1, 0][mask]
+            g.adjoint(lam_a, g_u)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = max(1, min(args.steps, 3))
+            e0.record(stream)
+            for _ in range(reps):
+                d_u0, d_a, ia = g.adjoint(lam_a, g_u)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_a = e0.elapsed_time(e1) / reps
+            adjoint = {"ms": round(ms_a, 3), "cycles": ia["cycles"], "rel_residual": ia["rel_residual"],
+                       "dL_da": [float(v) for v in d_a],
+                       "loss": "sum over bottom-layer centres inside a fire perimeter of u_x^2 + u_y^2"}
+            log(f"adjoint: {ms_a:.1f} ms, {ia['cycles']} cycles (cold transpose solve), "
+                f"dL/da {d_a[0]:.3e} {d_a[1]:.3e} {d_a[2]:.3e}")
+            del lam_a, u_a, g_u, d_u0, mask
         coupling = None
         if not args.no_coupling:
             # the steps around the solve: a coarse wind every 600 m (40 levels) to the
@@ -567,6 +594,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "mg_pcg": krylov,
+        "adjoint": adjoint,
         "coupling": coupling,
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
