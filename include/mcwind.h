@@ -156,8 +156,11 @@ void mcw_default_options(mcw_options* o);
  * arguments, checks det J > 0 at every Gauss point and element centre,
  * assembles the 27-point fine stiffness stencil from 2x2x2 Gauss quadrature,
  * chooses the coarse grids by the coarsening rule, forms the Galerkin
- * operators K_c = P^T K P and factors the coarsest one.  opts may be NULL
- * (defaults).  stream is a hipStream_t or NULL.  On success *out owns all of
+ * operators K_c = P^T K P and factors the coarsest one.  A coarse level always
+ * keeps a free node: where pairing layers between a fixed bottom and a fixed
+ * top would leave none, every plane is kept.  A grid with no free node at all
+ * (one layer with both z faces fixed, say) is accepted: its solves return
+ * lambda = 0 and u = u0.  opts may be NULL (defaults).  stream is a hipStream_t or NULL.  On success *out owns all of
  * the handle's device memory until mcw_destroy. */
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
                       mcw_handle** out);

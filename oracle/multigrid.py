@@ -97,6 +97,12 @@ def decide(X, Y, Z, a, rule, gamma, coarse_max):
             else:
                 keep.append(k + 1)
                 k += 1
+    # A coarse level keeps a free node: with both z faces fixed, dropping every
+    # interior plane would leave none, so then all planes are kept.
+    nxc = len(horizontal_keep(nx)) - 1 if ch else nx
+    nyc = len(horizontal_keep(ny)) - 1 if ch else ny
+    if n_free(nxc, nyc, len(keep) - 1, gamma) == 0:
+        keep = list(range(nz + 1))
     if not ch and len(keep) == nz + 1:
         if not can_h:
             return None

@@ -156,6 +156,11 @@ bool decide(const mcw_handle& h, const Dims& d, const Faces& fc, double h1, doub
       }
     }
   }
+  // a coarse level keeps a free node: with both z faces fixed, dropping every interior
+  // plane would leave none, so then all planes are kept
+  const Dims dc{ch ? (int)keep_every_other(d.nx).size() - 1 : d.nx,
+                ch ? (int)keep_every_other(d.ny).size() - 1 : d.ny, (int)keep_z.size() - 1};
+  if (free_count(dc, fc) == 0) keep_z = keep_all(d.nz);
   if (!ch && (int)keep_z.size() == d.nz + 1) {
     if (!can_h) return false;
     ch = true;
@@ -219,7 +224,7 @@ void factor_coarsest(mcw_handle& h) {
       }
   const int n = (int)idx.size();
   h.n_coarse = n;
-  if (n == 0) throw Error{MCW_SINGULAR, "the coarsest grid has no free nodes"};
+  if (n == 0) return;  // every node is fixed: lambda = 0 and no level has anything to solve
   std::vector<double> A((size_t)n * n, 0.0);
   for (int r = 0; r < n; ++r) {
     const size_t nd = (size_t)idx[r];
@@ -313,8 +318,10 @@ template <class T>
 void vcycle(mcw_handle& h, int l, T* x, const T* f) {
   Level& L = h.levels[l];
   if (l == (int)h.levels.size() - 1) {
-    launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(), f, x,
-                           h.stream);
+    // no free node (every node fixed): nothing to solve
+    if (h.n_coarse > 0)
+      launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(), f, x,
+                             h.stream);
     return;
   }
   const T* st = stencil_of<T>(L);
@@ -1008,8 +1015,9 @@ void coarse_t(mcw_handle& h, const T* r, T* e) {
   Level& L = h.levels.back();
   launch_relayout<T>(L.d, r, L.f.as<T>(), true, h.stream);
   launch_fill<T>(L.x.as<T>(), L.d.N(), T(0), h.stream);
-  launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(),
-                         L.f.as<T>(), L.x.as<T>(), h.stream);
+  if (h.n_coarse > 0)
+    launch_coarse_solve<T>(h.n_coarse, h.coarse_inv.as<double>(), h.coarse_idx.as<int>(),
+                           L.f.as<T>(), L.x.as<T>(), h.stream);
   launch_relayout<T>(L.d, L.x.as<T>(), e, false, h.stream);
 }
 

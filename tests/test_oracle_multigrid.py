@@ -145,6 +145,22 @@ def test_decision_stops_at_coarse_limit_and_full_rule():
     assert ch and keep == [0, 2, 4]
 
 
+def test_decision_keeps_a_free_plane_between_fixed_bottom_and_top():
+    """Two 1 m layers under 30 m spacing with lambda = 0 on the bottom and the top
+    (Gamma = the four sides): pairing the layers would leave a coarse grid with no
+    unknown, so both planes stay and only the horizontal directions coarsen; the
+    hierarchy then solves the system."""
+    X, Y, Z = _levels_grid(20, 20, np.ones(2))
+    gamma = 0b111100
+    assert mg.decide(X, Y, Z, [1, 1, 1], "operator", 1, 10) == (False, [0, 2])
+    assert mg.decide(X, Y, Z, [1, 1, 1], "operator", gamma, 10) == (True, [0, 1, 2])
+    levels = mg.build_hierarchy(X, Y, Z, [1, 1, 1], gamma, coarse_max=10)
+    assert len(levels) > 2 and all(L.free.size > 0 for L in levels)
+    f = np.random.default_rng(3).standard_normal(levels[0].free.size)
+    x, hist = mg.Multigrid(levels).solve(f, rtol=1e-10)
+    assert hist[-1] <= 1e-10
+
+
 # ---------------------------------------------------------------- convergence (Q11)
 
 def test_poisson_box_vcycle_factor_near_one_tenth():
