@@ -395,48 +395,107 @@ __global__ __launch_bounds__(256) void residual_batched(WorkList W) {
 
 // rc = P^T r: coarse node (I,J,K) gathers the fine nodes of its support with
 // weight 1 (the kept node) or 1/2 (a dropped neighbour), per direction.  A
-// thread marches up one coarse column: each fine plane's horizontal sum is
-// formed once and shared by the (at most two) coarse planes whose support
-// holds it.
-template <class T>
-__device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
+// thread marches up the fine planes under one coarse column, loading two
+// planes ahead: each fine plane's horizontal sum is formed once and added to
+// the (at most two) coarse planes whose support holds it, in the order of the
+// fine planes, so every coarse value is the same sum as a direct gather.
+template <class T, bool HC>
+__device__ __forceinline__ void restrict_column(const XferJob& X, int b) {
   const T* __restrict__ r = static_cast<const T*>(X.src);
   T* __restrict__ rc = static_cast<T*>(X.dst);
   const int I = (b % X.tiles_x) * BX + (threadIdx.x % BX);
   const int J = (b / X.tiles_x) * BY + (threadIdx.x / BX);
   if (I >= X.NXc || J >= X.NYc) return;
   const size_t pf = (size_t)X.NXf * X.NYf, pc = (size_t)X.NXc * X.NYc;
-  const bool colfree = !X.fc.x_fixed(I, X.NXc) && !X.fc.y_fixed(J, X.NYc);
-  const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZc);
-  const int xlo = X.mx.slo[I], xhi = X.mx.shi[I], xc = X.mx.ctr[I];
-  const int ylo = X.my.slo[J], yhi = X.my.shi[J], yc = X.my.ctr[J];
   const int NXef = (X.NXf + 1) >> 1, NXec = (X.NXc + 1) >> 1;
-  // horizontal part of P^T on fine plane pz
-  auto plane_sum = [&](int pz) {
+  T* __restrict__ out = rc + (size_t)J * X.NXc + sx(I, NXec);
+  const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZc);
+  const bool colfree = !X.fc.x_fixed(I, X.NXc) && !X.fc.y_fixed(J, X.NYc);
+  if (!colfree || kf > kl) {
+    for (int K = 0; K < X.NZc; ++K) out[(size_t)K * pc] = T(0);
+    return;
+  }
+  for (int K = 0; K < kf; ++K) out[(size_t)K * pc] = T(0);
+  for (int K = kl + 1; K < X.NZc; ++K) out[(size_t)K * pc] = T(0);
+  // the horizontal support (HC: the directions are coarsened): the kept index
+  // and its dropped neighbours, an absent neighbour repeating the kept index
+  // with weight 0; without horizontal coarsening, the node itself
+  constexpr int S = HC ? 9 : 1;
+  const int xc = X.mx.ctr[I], xlo = X.mx.slo[I], xhi = X.mx.shi[I];
+  const int yc = X.my.ctr[J], ylo = X.my.slo[J], yhi = X.my.shi[J];
+  const T wx[3] = {xlo < xc ? T(0.5) : T(0), T(1), xhi > xc ? T(0.5) : T(0)};
+  const T wy[3] = {ylo < yc ? T(0.5) : T(0), T(1), yhi > yc ? T(0.5) : T(0)};
+  size_t off[S];
+  if (HC) {
+    const int ox[3] = {sx(xlo, NXef), sx(xc, NXef), sx(xhi, NXef)};
+    const int oy[3] = {ylo, yc, yhi};
+#pragma unroll
+    for (int a = 0; a < S / 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) off[3 * a + c] = (size_t)oy[a] * X.NXf + ox[c];
+  } else {
+    off[0] = (size_t)J * X.NXf + sx(I, NXef);
+  }
+  auto load_plane = [&](int pz, T (&v)[S]) {
+    const T* __restrict__ pl = r + (size_t)pz * pf;
+#pragma unroll
+    for (int q = 0; q < S; ++q) v[q] = pl[off[q]];
+  };
+  auto plane_sum = [&](const T (&v)[S]) {
+    if (!HC) return v[0];
     T h = T(0);
-    for (int py = ylo; py <= yhi; ++py) {
-      const T* row = r + (size_t)pz * pf + (size_t)py * X.NXf;
-      T v = T(0);
-      for (int px = xlo; px <= xhi; ++px) v += (px == xc ? T(1) : T(0.5)) * row[sx(px, NXef)];
-      h += (py == yc ? T(1) : T(0.5)) * v;
+#pragma unroll
+    for (int a = 0; a < S / 3; ++a) {
+      T row = T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) row += wx[c] * v[3 * a + c];
+      h += wy[a] * row;
     }
     return h;
   };
-  int last_pz = -1;
-  T last_h = T(0);
-  for (int K = 0; K < X.NZc; ++K) {
-    T v = T(0);
-    if (colfree && K >= kf && K <= kl) {
-      const int zlo = X.mz.slo[K], zhi = X.mz.shi[K], zc = X.mz.ctr[K];
-      for (int pz = zlo; pz <= zhi; ++pz) {
-        const T h = pz == last_pz ? last_h : plane_sum(pz);
-        last_pz = pz;
-        last_h = h;
-        v += (pz == zc ? T(1) : T(0.5)) * h;
+  // fine planes of the free coarse planes' supports.  Plane pz + 2 is loaded
+  // while plane pz is summed (clamped to the last plane, so that every load is
+  // issued unconditionally and stays in flight); the three buffers rotate by
+  // unrolling, not by copies, which would wait for the loads.
+  const int p0 = X.mz.slo[kf], p1 = X.mz.shi[kl];
+  T acc = T(0);
+  auto step = [&](int pz, const T (&cur)[S], T (&ahead)[S]) {
+    load_plane(min(pz + 2, p1), ahead);
+    const T h = plane_sum(cur);
+    const int Klo = X.mz.lo[pz], Khi = X.mz.hi[pz];
+    if (Klo == Khi) {
+      // kept plane of Klo, weight 1; Klo is complete unless a dropped plane follows
+      acc += T(1) * h;
+      if (X.mz.shi[Klo] == pz) {
+        out[(size_t)Klo * pc] = acc;
+        acc = T(0);
       }
+    } else {
+      // dropped plane between Klo and Khi = Klo + 1, weight 1/2 to each: it
+      // ends the support of Klo and starts that of Khi
+      acc += T(0.5) * h;
+      out[(size_t)Klo * pc] = Klo >= kf ? acc : T(0);
+      acc = T(0);
+      acc += T(0.5) * h;
     }
-    rc[(size_t)K * pc + (size_t)J * X.NXc + sx(I, NXec)] = v;
+  };
+  T b0[S], b1[S], b2[S];
+  load_plane(p0, b0);
+  load_plane(min(p0 + 1, p1), b1);
+  for (int pz = p0;; pz += 3) {
+    step(pz, b0, b2);
+    if (pz + 1 > p1) break;
+    step(pz + 1, b1, b0);
+    if (pz + 2 > p1) break;
+    step(pz + 2, b2, b1);
+    if (pz + 3 > p1) break;
   }
+}
+
+template <class T>
+__device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
+  if (X.NXc != X.NXf) restrict_column<T, true>(X, b);
+  else restrict_column<T, false>(X, b);
 }
 
 template <class T>
@@ -450,6 +509,10 @@ __global__ __launch_bounds__(256) void restrict_batched(WorkList W) {
 }
 
 // x += P e: fine node p interpolates from coarse lo[p] and hi[p] per direction.
+//
+// Column version (every level in the batched launch; levels that keep every
+// horizontal node in the single-grid launch): a thread updates one fine column;
+// the last two coarse values are kept, as consecutive fine planes share them.
 template <class T>
 __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
   const T* __restrict__ e = static_cast<const T*>(X.src);
@@ -498,6 +561,129 @@ __device__ __forceinline__ void prolong_body(const XferJob& X, int b) {
 template <class T>
 __global__ __launch_bounds__(256) void prolong_kernel(XferJob X) {
   prolong_body<T>(X, xcd_remap(blockIdx.x, X.nblocks));
+}
+
+// Single-grid prolongation on horizontally coarsened levels (every other node
+// kept in x and y).  A thread owns the fine columns (2q, 2q+1) x (2J, 2J+1)
+// around coarse column (q, J); they interpolate from the coarse columns
+// (q, q+1) x (J, J+1) only, each loaded once per coarse plane instead of once
+// per fine column.  The column is updated D fine planes at a time: the chunk's
+// coarse planes (a uniform count, at most D+1) and the x of its planes are all
+// loaded before the first is used.  A kept index takes the same coarse value
+// twice and 0.5 (v + v) = v exactly, so every mean is formed as in the column
+// version (x, then y, then z, low index first) and the result is the same to
+// the bit.  The job's tiles cover the coarse columns.  (The body is written in
+// the kernel itself: through a device function taking the job by reference the
+// compiler lowers the choice of coarse planes with per-lane index chains and
+// needs half again as many registers.)
+template <class T, int D>
+__global__ __launch_bounds__(256) void prolong_pairs_kernel(XferJob X) {
+  const int b = blockIdx.x;
+  const T* __restrict__ e = static_cast<const T*>(X.src);
+  T* __restrict__ x = static_cast<T*>(X.dst);
+  const int qc = (b % X.tiles_x) * BX + (threadIdx.x % BX);
+  const int Jc = (b / X.tiles_x) * BY + (threadIdx.x / BX);
+  if (qc >= X.NXc || Jc >= X.NYc) return;
+  const int kf = X.fc.k_first(), kl = X.fc.k_last(X.NZf);
+  if (kf > kl) return;
+  const size_t pf = (size_t)X.NXf * X.NYf, pc = (size_t)X.NXc * X.NYc;
+  const int NXef = (X.NXf + 1) >> 1, NXec = (X.NXc + 1) >> 1;
+  // fine column c = 2w + u is (2q+u, 2J+w): whether it exists and is free, and
+  // its row-split offset in a plane
+  bool act[4];
+  size_t fo[4];
+  // per fine x index 2q+u (y index 2J+w): 2 for the mean of coarse q and q+1,
+  // else which of the two it is (the last fine node is kept even when odd)
+  int cx[2], cy[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = 2 * qc + u;
+    const bool in = i < X.NXf;
+    const int lo = in ? X.mx.lo[i] : qc, hi = in ? X.mx.hi[i] : qc;
+    cx[u] = lo != hi ? 2 : (lo == qc ? 0 : 1);
+  }
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const int j = 2 * Jc + w;
+    const bool in = j < X.NYf;
+    const int lo = in ? X.my.lo[j] : Jc, hi = in ? X.my.hi[j] : Jc;
+    cy[w] = lo != hi ? 2 : (lo == Jc ? 0 : 1);
+  }
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = 2 * qc + u, j = 2 * Jc + w;
+      act[2 * w + u] = i < X.NXf && j < X.NYf && !X.fc.x_fixed(i, X.NXf) && !X.fc.y_fixed(j, X.NYf);
+      fo[2 * w + u] = act[2 * w + u] ? (size_t)j * X.NXf + sx(i, NXef) : 0;
+    }
+  // coarse columns (q, J), (q+1, J), (q, J+1), (q+1, J+1), clamped to the grid
+  const int q1 = min(qc + 1, X.NXc - 1), J1 = min(Jc + 1, X.NYc - 1);
+  const size_t co[4] = {(size_t)Jc * X.NXc + sx(qc, NXec), (size_t)Jc * X.NXc + sx(q1, NXec),
+                        (size_t)J1 * X.NXc + sx(qc, NXec), (size_t)J1 * X.NXc + sx(q1, NXec)};
+  // the four fine columns' values v on one coarse plane from its 2 x 2 values c
+  auto horizontal = [&](const T (&c)[4], T (&v)[4]) {
+    T row[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        row[r][u] = cx[u] == 2 ? T(0.5) * (c[2 * r] + c[2 * r + 1]) : c[2 * r + cx[u]];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        v[2 * w + u] = cy[w] == 2 ? T(0.5) * (row[0][u] + row[1][u]) : row[cy[w]][u];
+  };
+  constexpr int M = D + 1;
+  for (int k0 = kf; k0 <= kl; k0 += D) {
+    const int z0 = X.mz.lo[k0], z1 = X.mz.hi[min(k0 + D - 1, kl)];
+    T cv[M][4], xv[D][4];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (z0 + m <= z1) {
+        const T* __restrict__ p = e + (size_t)(z0 + m) * pc;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cv[m][c] = p[co[c]];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      if (k0 + t <= kl) {
+        const T* __restrict__ p = x + (size_t)(k0 + t) * pf;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xv[t][c] = p[fo[c]];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (z0 + m <= z1) {
+        T v[4];
+        horizontal(cv[m], v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cv[m][c] = v[c];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      const int k = k0 + t;
+      if (k <= kl) {
+        // fine plane k between coarse planes lo[k] and hi[k] (equal when kept)
+        const int da = X.mz.lo[k] - z0, db = X.mz.hi[k] - z0;
+        T* __restrict__ p = x + (size_t)k * pf;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T va = cv[0][c], vb = cv[0][c];
+#pragma unroll
+          for (int m = 1; m < M; ++m) {
+            va = da == m ? cv[m][c] : va;
+            vb = db == m ? cv[m][c] : vb;
+          }
+          if (act[c]) p[fo[c]] = xv[t][c] + (da == db ? va : T(0.5) * (va + vb));
+        }
+      }
+    }
+  }
 }
 
 template <class T>
@@ -1106,7 +1292,15 @@ void launch_prolong_dims(const Dims& df, const Dims& dc, const Faces& fc, const 
                          const DirMapDev& my, const DirMapDev& mz, const T* e, T* x,
                          hipStream_t s) {
   const XferJob X = xfer_job(df, dc, fc, mx, my, mz, e, x, false);
-  prolong_kernel<T><<<X.nblocks, 256, 0, s>>>(X);
+  if (X.NXc != X.NXf) {
+    // horizontally coarsened: one thread per coarse column, tiles over the coarse grid
+    XferJob P = X;
+    P.tiles_x = (P.NXc + BX - 1) / BX;
+    P.nblocks = P.tiles_x * ((P.NYc + BY - 1) / BY);
+    prolong_pairs_kernel<T, 4><<<P.nblocks, 256, 0, s>>>(P);
+  } else {
+    prolong_kernel<T><<<X.nblocks, 256, 0, s>>>(X);
+  }
   MCW_CHECK_LAUNCH();
 }
 

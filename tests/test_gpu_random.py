@@ -87,3 +87,35 @@ def test_fixed_bottom_and_top_on_two_layers():
     assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-12
     assert gc.rel_err(lam.cpu().numpy(), lam_ref) < 1e-8
     assert gc.rel_err(u.cpu().numpy() - u0, u_ref - u0) < 1e-8
+
+
+@pytest.mark.parametrize("rule", ["operator", "full"])
+@pytest.mark.parametrize("seed", range(16))
+def test_random_transfers_match_oracle(seed, rule):
+    """Restriction P^T r and prolongation x + P e on every level of the random
+    cases (fixed or free bottom and top planes, with and without horizontal
+    coarsening, merged and kept layers) against the oracle's P, in the
+    handle's precision."""
+    from oracle import multigrid as omg
+    from paper_2101_08453_amd import mcwind
+    p, opts = _case(seed)
+    print(f"[case] transfers seed {seed} rule {rule}", flush=True)
+    g, _ = mcwind.grid_from_problem(p, coarsen_rule=rule, **opts)
+    levels = omg.build_hierarchy(p.X, p.Y, p.Z, p.a, p.gamma, rule=rule,
+                                 coarse_max=opts["coarse_direct_max"])
+    assert [g.level(l)["dims"] for l in range(len(levels))] == [(L.nx, L.ny, L.nz) for L in levels]
+    f32 = opts["precision"] == "fp32_refine"
+    dt, tol = (torch.float32, 1e-6) if f32 else (torch.float64, 1e-14)
+    rng = np.random.default_rng(500 + seed)
+    for l in range(len(levels) - 1):
+        L, C = levels[l], levels[l + 1]
+        fs, cs = (L.nz + 1, L.ny + 1, L.nx + 1), (C.nz + 1, C.ny + 1, C.nx + 1)
+        r = torch.from_numpy(rng.standard_normal(L.mask.size) * L.mask).to(dt)
+        rn = r.double().numpy()
+        rc = g.restrict(l, r.reshape(fs).cuda()).cpu().double().numpy().ravel()
+        assert gc.rel_err(rc, np.where(C.mask, L.P_full.T @ rn, 0.0)) < tol, f"restrict level {l}"
+        e = torch.from_numpy(rng.standard_normal(C.mask.size) * C.mask).to(dt)
+        x = torch.from_numpy(rng.standard_normal(L.mask.size) * L.mask).to(dt)
+        xg = g.prolong(l, e.reshape(cs).cuda(), x.reshape(fs).cuda()).cpu().double().numpy().ravel()
+        ref = x.double().numpy() + np.where(L.mask, L.P_full @ e.double().numpy(), 0.0)
+        assert gc.rel_err(xg, ref) < tol, f"prolong level {l}"
