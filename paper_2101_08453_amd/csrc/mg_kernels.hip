@@ -262,8 +262,14 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
 // block barrier between the two halves keeps the order of the separate passes
 // and gives the same result bit for bit, while x of rows j-1, j, j+1 is
 // fetched once for both colours.
+// Threads per block of the fused pass: 1024, except the FP64 line smoother,
+// whose Thomas sweep needs more than the 128 registers a 1024-thread block
+// leaves per lane (it spilled); with 512 threads it has 256.
+template <class T, bool LINE>
+constexpr int fused_threads() { return sizeof(T) == 8 && LINE ? 512 : 1024; }
+
 template <class T, bool REV, bool LINE>
-__global__ __launch_bounds__(1024) void gs_fused_kernel(ColJob J0, ColJob J1) {
+__global__ __launch_bounds__((fused_threads<T, LINE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
   const int j = 2 * (int)blockIdx.x + J0.cj;
   for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
     smooth_column<T, REV, LINE>(J0, 2 * ii + J0.ci, j);
@@ -1002,7 +1008,7 @@ void smooth_sweep_t(const Dims& d, const Faces& fc, const T* st, const T* f, T* 
       const ColJob J1 = col_job(d, fc, st, f, x, cbuf, c1, 1);
       if (J0.ncy <= 0) continue;
       const int cols = std::max(J0.ncx, J1.ncx);
-      const int threads = std::min(1024, std::max(64, (cols + 63) / 64 * 64));
+      const int threads = std::min(fused_threads<T, LINE>(), std::max(64, (cols + 63) / 64 * 64));
       if (reverse)
         gs_fused_kernel<T, true, LINE><<<J0.ncy, threads, 0, s>>>(J0, J1);
       else
