@@ -103,16 +103,17 @@ def kernel_table(g, stream, n_free):
         g.run_kernel(0, kernel, 1)  # warm
         return time_on_stream(stream, lambda: g.run_kernel(0, kernel, reps), 1) / (reps * launches_per_rep)
 
-    # a sweep updates every free node once: 27 FP32 coefficients and a pad (112 B),
-    # f, and x read and written once per node = 120 B.  It runs as 4 colour-pass
-    # launches, or as 2 when the level uses the fused two-colour pass.
+    # a sweep updates every free node once: the 26 stored FP32 off-diagonal
+    # coefficients (104 B; the diagonal is formed from them), f (4 B), and x read
+    # and written (8 B) = 116 B.  It runs as 4 colour-pass launches, or as 2 when
+    # the level uses the fused two-colour pass.
     launches = 2 if g.tile_rows(0)[0] == 0 else 4
     ms = timed("smooth", 8, launches)
-    b = 120.0 * n_free / launches
+    b = 116.0 * n_free / launches
     out["gs_colour_pass_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6,
                                  "launches_per_sweep": launches}
     ms = timed("residual", 4)
-    b = (112.0 + 4 + 4 + 4) * N
+    b = (104.0 + 4 + 4 + 4) * N  # stencil, x, f, r
     out["residual_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
     ms = timed("restrict", 4)
     b = 4.0 * N + 4.0 * Nc

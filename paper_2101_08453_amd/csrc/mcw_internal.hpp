@@ -85,11 +85,40 @@ struct StLayout {
   }
 };
 
+// FP64 stencils: SW slots per node (the 27 coefficients and a pad), in groups of
+// two doubles interleaved over 64 consecutive nodes.
 template <class T>
-__host__ __device__ inline size_t st_entry(size_t p, int o) {
-  constexpr int E = 16 / (int)sizeof(T);
-  constexpr int G = SW / E;
-  return ((p >> 6) * G + o / E) * (size_t)(64 * E) + (p & 63) * E + (o % E);
+__host__ __device__ inline size_t st_entry(size_t p, int o);
+template <>
+__host__ __device__ inline size_t st_entry<double>(size_t p, int o) {
+  constexpr int G = SW / 2;
+  return ((p >> 6) * G + o / 2) * (size_t)128 + (p & 63) * 2 + (o % 2);
+}
+
+// FP32 stencils store only the 26 off-diagonal coefficients: the diagonal of
+// the FP32 operator is minus their sum (stencil_diag), so it is formed where
+// it is used instead of being read.  Per 64 consecutive nodes: six groups of
+// four floats (slots 0-23) and one group of two (slots 24, 25), each
+// interleaved over the 64 nodes; 104 B per node.
+constexpr int SW32 = 26;
+__host__ __device__ constexpr int slot32(int o) { return o < 13 ? o : o - 1; }  // o != 13
+template <>
+__host__ __device__ inline size_t st_entry<float>(size_t p, int o) {
+  const int s = slot32(o);
+  const size_t base = (p >> 6) * (size_t)(64 * SW32);
+  return s < 24 ? base + (size_t)(s >> 2) * 256 + (p & 63) * 4 + (s & 3)
+                : base + 1536 + (p & 63) * 2 + (s - 24);
+}
+
+// Diagonal of the FP32 operator from its off-diagonal coefficients a[o],
+// o != 13: minus their sum, accumulated in FP64 in the order of o and rounded
+// once, so that constants stay in the null space of the unconstrained FP32
+// operator as they are for K.
+__host__ __device__ inline float stencil_diag(const float* a) {
+  double sum = 0.0;
+  for (int o = 0; o < 27; ++o)
+    if (o != 13) sum += (double)a[o];
+  return (float)(-sum);
 }
 
 // ---------------------------------------------------------------- grid geometry

@@ -41,14 +41,25 @@ __device__ __forceinline__ StLayout dev_layout(int NX, int NY) {
 // with non-temporal loads: a pass streams each stencil value once, so it
 // should not displace the x values that neighbouring columns reuse.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+// FP32: the 26 stored off-diagonal coefficients into a[o], o != 13, and the
+// diagonal a[13] formed from them (the same value the rounding kernel defines).
 __device__ __forceinline__ void load_stencil_nt(const float* __restrict__ st, size_t p, float a[SW]) {
-  const f32x4* v = reinterpret_cast<const f32x4*>(st) + (p >> 6) * (SW / 4) * 64 + (p & 63);
+  const float* base = st + (p >> 6) * (size_t)(64 * SW32);
+  const f32x4* v = reinterpret_cast<const f32x4*>(base) + (p & 63);
+  float b[SW32];
 #pragma unroll
-  for (int g = 0; g < SW / 4; ++g) {
+  for (int g = 0; g < 6; ++g) {
     const f32x4 t = __builtin_nontemporal_load(v + g * 64);
-    a[4 * g] = t.x; a[4 * g + 1] = t.y; a[4 * g + 2] = t.z; a[4 * g + 3] = t.w;
+    b[4 * g] = t.x; b[4 * g + 1] = t.y; b[4 * g + 2] = t.z; b[4 * g + 3] = t.w;
   }
+  const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(base + 1536) + (p & 63));
+  b[24] = t.x; b[25] = t.y;
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+    if (o != 13) a[o] = b[slot32(o)];
+  a[13] = stencil_diag(a);
 }
 __device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, size_t p, double a[SW]) {
   const f64x2* v = reinterpret_cast<const f64x2*>(st) + (p >> 6) * (SW / 2) * 64 + (p & 63);
@@ -756,16 +767,9 @@ __global__ __launch_bounds__(256) void round_stencil_kernel(const double* __rest
   if (n >= N) return;
   const StLayout L = dev_layout(NX, NY);
   const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
-  double sum = 0.0;
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    if (o == 13) continue;
-    const float v = (float)s64[st_entry<double>(p, o)];
-    s32[st_entry<float>(p, o)] = v;
-    sum += (double)v;
-  }
-  s32[st_entry<float>(p, 13)] = (float)(-sum);
-  s32[st_entry<float>(p, 27)] = 0.f;
+  for (int o = 0; o < 27; ++o)
+    if (o != 13) s32[st_entry<float>(p, o)] = (float)s64[st_entry<double>(p, o)];
 }
 
 template <class T>
@@ -776,6 +780,15 @@ __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T
   const size_t o = gid / N, n = gid % N;
   const StLayout L = dev_layout(NX, NY);
   const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+  if constexpr (sizeof(T) == 4) {
+    if (o == 13) {
+      float a[27];
+#pragma unroll
+      for (int q = 0; q < 27; ++q) a[q] = q == 13 ? 0.f : s[st_entry<float>(p, q)];
+      out[gid] = stencil_diag(a);
+      return;
+    }
+  }
   out[gid] = s[st_entry<T>(p, (int)o)];
 }
 

@@ -866,7 +866,7 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
       launch_rap(L.d, C.d, L.dmx, L.dmy, L.dmz, L.st64.as<double>(), C.st64.as<double>(), h.stream);
     }
     if (f32) {
-      L.st32.alloc(SW * L.d.layout().nodes * sizeof(float));
+      L.st32.alloc(SW32 * L.d.layout().nodes * sizeof(float));
       launch_round_stencil(L.d, L.st64.as<double>(), L.st32.as<float>(), h.stream);
       if (l + 1 < h.levels.size()) {
         MCW_HIP(hipStreamSynchronize(h.stream));

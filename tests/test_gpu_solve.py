@@ -243,28 +243,33 @@ def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precisi
     assert float((lam - lam2).abs().max() / lam2.abs().max()) < 1e-8
 
 
+@pytest.mark.parametrize("dims", [(160, 120, 8), (2100, 5, 5)])
 @pytest.mark.parametrize("smoother", ["point", "line"])
 @pytest.mark.parametrize("precision", ["fp32_refine", "fp64"])
-def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision, smoother):
+def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision, smoother, dims):
     """The fused two-colour pass (one block per row) and the four separate colour
-    passes give the same sweep bit for bit, forward and reverse."""
+    passes give the same sweep bit for bit, forward and reverse.  The 2100-element
+    rows hold about 1050 columns of a colour, more than a block's threads (1024,
+    or 512 for the FP64 line smoother), so each thread takes several columns."""
     mcwind = _mcw()
-    p = inputs.hills_problem(160, 120, 8, 4, 5, a=(1.0, 1.0, 2.0))
+    nx, ny, nz = dims
+    p = inputs.hills_problem(nx, ny, nz, 4, 5, a=(1.0, 1.0, 2.0))
     tag = "f32" if precision == "fp32_refine" else "f64"
     key = "gsf" if smoother == "point" else "gsl"
+    shp = f"{nx + 1}x{ny + 1}x{nz + 1}"
     grids = []
     for shape in (0, 4):
         cache = tmp_path / f"tune{shape}.json"
-        cache.write_text('{\n  "gfx950|%s|161x121x9|%s": %d,\n  "gfx950|res|161x121x9|%s": 4\n}\n'
-                         % (key, tag, shape, tag))
+        cache.write_text('{\n  "gfx950|%s|%s|%s": %d,\n  "gfx950|res|%s|%s": 4\n}\n'
+                         % (key, shp, tag, shape, shp, tag))
         monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
         g, u0 = mcwind.grid_from_problem(p, precision=precision, krylov=True, smoother=smoother)
         assert g.tile_rows(0)[0] == shape
         grids.append(g)
     dt = torch.float32 if precision == "fp32_refine" else torch.float64
     rng = np.random.default_rng(3)
-    x0 = torch.from_numpy(rng.standard_normal((9, 121, 161))).to("cuda", dt)
-    f = torch.from_numpy(rng.standard_normal((9, 121, 161))).to("cuda", dt)
+    x0 = torch.from_numpy(rng.standard_normal((nz + 1, ny + 1, nx + 1))).to("cuda", dt)
+    f = torch.from_numpy(rng.standard_normal((nz + 1, ny + 1, nx + 1))).to("cuda", dt)
     out = []
     for g in grids:
         x = x0.clone()
