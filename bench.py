@@ -591,7 +591,8 @@ def main():
                   "rel_residual": info["rel_residual"], "rel_divergence": info["rel_divergence"],
                   "rho": info["rho"], "setup_s": round(setup_s, 2), "ms_rhs": info["ms_rhs"],
                   "ms_cycles": info["ms_cycles"], "ms_outer": info["ms_outer"],
-                  "ms_finish": info["ms_finish"], "levels": info["levels"]},
+                  "ms_finish": info["ms_finish"], "levels": info["levels"],
+                  "history": [float(f"{v:.3e}") for v in info["history"]]},
         "roofline": roof,
         "kernels": kernels,
         "mg_pcg": krylov,

@@ -433,6 +433,11 @@ int pcg_inner(mcw_handle& h, const Krylov<T>& v, int m_max, double rr_stop) {
 
 // Steps for the next inner solve: enough to reduce the residual by `target`
 // at the measured rate, within [1, cap].
+// At most this many FP32 V-cycles per refinement step: enough for the 3e-5
+// reduction an FP32 inner solve is asked for at rates up to about 0.6 (18 at
+// 0.55), so that a slow solve needs no extra FP64 residual evaluations.
+constexpr int kMaxInnerCycles = 20;
+
 int inner_steps(double target, double rho, int cap) {
   const int m = (int)std::ceil(std::log(target) / std::log(rho));
   return std::max(1, std::min(m, cap));
@@ -523,9 +528,12 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
       }
       rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / prev_m)));
     }
-    // reduce to the tolerance in one step, but not below what FP32 can resolve
-    int m = h.opt.inner_cycles > 0 ? h.opt.inner_cycles
-                                   : inner_steps(std::max(tol / pg.rel, 3e-5), rho_est, 12);
+    // reduce to the tolerance in one step, but not below what FP32 can resolve.
+    // (Aiming lower, at half the tolerance, trades a refinement step of one FP64
+    // residual for an extra V-cycle, which costs about four times as much.)
+    int m = h.opt.inner_cycles > 0
+                ? h.opt.inner_cycles
+                : inner_steps(std::max(tol / pg.rel, 3e-5), rho_est, kMaxInnerCycles);
     m = std::min(m, h.opt.max_cycles - pg.cycles);
     // scale the residual by a power of two to O(1) before rounding it to FP32
     const double rms = std::sqrt(rr / nfree);
@@ -1317,9 +1325,7 @@ class Batch {
         if (!S.active) continue;
         int mi = h.opt.inner_cycles;
         if (mi <= 0) {
-          const double target = std::max(tol / S.rel, 3e-5);
-          mi = (int)std::ceil(std::log(target) / std::log(S.rho_est));
-          mi = std::max(1, std::min(mi, 12));
+          mi = inner_steps(std::max(tol / S.rel, 3e-5), S.rho_est, kMaxInnerCycles);
         }
         mi = std::min(mi, h.opt.max_cycles - S.cycles);
         want = std::max(want, mi);
