@@ -795,20 +795,34 @@ __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T
 // ---------------------------------------------------------------- coarsest level
 
 // e[idx] = Kinv r[idx] for the free coarsest nodes (Kinv symmetric, so column
-// `row` is read with consecutive threads on consecutive addresses).
+// `row` is read with consecutive lanes on consecutive addresses).  A block of
+// four waves computes 64 rows: wave w sums the w-th quarter of the columns, and
+// the four partial sums are added in wave order.  LDS: r (n doubles), then the
+// 4 x 64 partial sums.
+constexpr int COARSE_ROWS = 64;
 template <class T>
 __device__ __forceinline__ void coarse_body(const CoarseJob& C, int b, double* rs) {
   const T* __restrict__ r = static_cast<const T*>(C.r);
   T* __restrict__ e = static_cast<T*>(C.e);
   const int n = C.n;
-  __syncthreads();  // rs may still be read by the previous work item
+  double* part = rs + n;
+  __syncthreads();  // rs and part may still be read by the previous work item
   for (int t = threadIdx.x; t < n; t += blockDim.x) rs[t] = (double)r[C.idx[t]];
   __syncthreads();
-  const int row = b * blockDim.x + threadIdx.x;
-  if (row >= n) return;
+  const int lane = threadIdx.x % COARSE_ROWS, w = threadIdx.x / COARSE_ROWS;
+  const int row = b * COARSE_ROWS + lane;
+  const int q = (n + 3) / 4, j0 = min(n, w * q), j1 = min(n, j0 + q);
   double s = 0.0;
-  for (int jj = 0; jj < n; ++jj) s += C.inv[(size_t)jj * n + row] * rs[jj];
-  e[C.idx[row]] = (T)s;
+  if (row < n) {
+    // unrolled so that several columns' loads are in flight; one sum, in order
+#pragma unroll 8
+    for (int jj = j0; jj < j1; ++jj) s += C.inv[(size_t)jj * n + row] * rs[jj];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (w == 0 && row < n)
+    e[C.idx[row]] = (T)(((part[lane] + part[COARSE_ROWS + lane]) + part[2 * COARSE_ROWS + lane]) +
+                        part[3 * COARSE_ROWS + lane]);
 }
 
 template <class T>
@@ -993,7 +1007,7 @@ XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDe
 }
 
 CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, void* e) {
-  CoarseJob C{n, inv, idx, r, e, (n + 255) / 256};
+  CoarseJob C{n, inv, idx, r, e, (n + COARSE_ROWS - 1) / COARSE_ROWS};
   return C;
 }
 
@@ -1327,7 +1341,8 @@ template <class T>
 void launch_coarse_solve(int n, const double* inv, const int* idx, const T* r, T* e,
                          hipStream_t s) {
   const CoarseJob C = coarse_job(n, inv, idx, r, e);
-  coarse_solve_kernel<T><<<C.nblocks, 256, (size_t)n * sizeof(double), s>>>(C);
+  coarse_solve_kernel<T>
+      <<<C.nblocks, 4 * COARSE_ROWS, (size_t)(n + 4 * COARSE_ROWS) * sizeof(double), s>>>(C);
   MCW_CHECK_LAUNCH();
 }
 
@@ -1487,7 +1502,8 @@ void launch_prolong_batched(const WorkList& W, hipStream_t s) {
 template <class T>
 void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s) {
   if (W.total <= 0) return;
-  coarse_solve_batched<T><<<batched_grid(W.total), 256, (size_t)max_n * sizeof(double), s>>>(W);
+  coarse_solve_batched<T><<<batched_grid(W.total), 4 * COARSE_ROWS,
+                            (size_t)(max_n + 4 * COARSE_ROWS) * sizeof(double), s>>>(W);
   MCW_CHECK_LAUNCH();
 }
 

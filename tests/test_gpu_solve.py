@@ -67,7 +67,11 @@ def test_fp64_residual_history_matches_oracle_multigrid():
     hist = np.array(hist)
     assert abs(len(gh) - len(hist)) <= 1
     n = min(len(gh), len(hist))
-    big = hist[:n] > 1e-10  # below that both histories sit on FP64 rounding
+    # The two coarsest solves (dense LU here, the explicit inverse on the GPU) and
+    # the sums round differently; that noise is relative to ||f||, so relative
+    # to the residual it grows about tenfold per decade: 2e-7 at 2.6e-9, 1.2e-6
+    # at 1.8e-10.  Steps above 1e-9 carry the comparison.
+    big = hist[:n] > 1e-9
     assert big.sum() >= 5
     assert np.allclose(gh[:n][big], hist[:n][big], rtol=1e-6, atol=0)
     assert info["rho"] < 0.35  # the paper reports about 0.28 with four smoothing steps
