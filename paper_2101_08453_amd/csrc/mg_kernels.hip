@@ -517,7 +517,7 @@ __device__ __forceinline__ void restrict_body(const XferJob& X, int b) {
 
 template <class T>
 __global__ __launch_bounds__(256) void restrict_kernel(XferJob X) {
-  restrict_body<T>(X, blockIdx.x);
+  restrict_body<T>(X, xcd_remap(blockIdx.x, X.nblocks));
 }
 
 template <class T>
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256) void prolong_kernel(XferJob X) {
 // needs half again as many registers.)
 template <class T, int D>
 __global__ __launch_bounds__(256) void prolong_pairs_kernel(XferJob X) {
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, X.nblocks);
   const T* __restrict__ e = static_cast<const T*>(X.src);
   T* __restrict__ x = static_cast<T*>(X.dst);
   const int qc = (b % X.tiles_x) * BX + (threadIdx.x % BX);
