@@ -45,12 +45,17 @@ def _dev_cw(cw):
     return d
 
 
+@pytest.mark.parametrize("fine_coarse", [False, True])
 @pytest.mark.parametrize("name", gc.CASES)
-def test_interpolation_matches_oracle(name):
+def test_interpolation_matches_oracle(name, fine_coarse):
+    """fine_coarse: coarse columns every 10 m, so that the columns around a tile of
+    64 x 4 element columns do not fit in the kernel's LDS and it reads them from
+    global memory; otherwise they are staged."""
     p = gc.problem(name)
-    print(f"[case] interp {name}", flush=True)
+    print(f"[case] interp {name} fine_coarse {fine_coarse}", flush=True)
     g, _ = _mcw().grid_from_problem(p)
-    cw = _coarse(p, spacing=max(60.0, (p.X.max() - p.X.min()) / 5.0), shift=0.3)
+    spacing = 10.0 if fine_coarse else max(60.0, (p.X.max() - p.X.min()) / 5.0)
+    cw = _coarse(p, spacing=spacing, shift=0.3)
     u0 = g.interp_wind(_dev_cw(cw)).cpu().numpy()
     ref = coupling.interp_wind(p.X, p.Y, p.Z, cw)
     _, zeta = coupling.heights_above_ground(p.X, p.Y, p.Z)
