@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-coupling", action="store_true",
                     help="skip timing the steps around the solve")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
+    ap.add_argument("--no-fp16", action="store_true",
+                    help="skip the solves with FP16 stencils (option stencil_fp16)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules", "configs"],
                     help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
                          "rules: coarsening rules across penalties and layer stretching")
@@ -535,6 +537,41 @@ def main():
                 f"rel res {ik['rel_residual']:.2e}, lambda diff {diff:.2e}")
             del gk
             torch.cuda.empty_cache()
+        half = None
+        if not args.no_fp16:
+            # the same solve with the V-cycle's stencils kept in FP16 (arithmetic
+            # still FP32, refinement FP64): the multigrid iteration, then CG
+            half = {}
+            for kry in (False, True):
+                t0 = time.perf_counter()
+                gh = mcwind.Grid(X, Y, Z, p.a, precision="fp32_refine", rtol=1e-8, krylov=kry,
+                                 stencil_fp16=True)
+                sh = time.perf_counter() - t0
+                lamh = torch.empty_like(lam_prev)
+                lamh.copy_(lam_prev)
+                gh.solve(u0p, lam=lamh, want_u=False)  # warm-up (graph capture)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                reps = max(1, min(args.steps, 3))
+                e0.record(stream)
+                for _ in range(reps):
+                    lamh.copy_(lam_prev)
+                    _, _, ih = gh.solve(u0p, lam=lamh)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                msh = e0.elapsed_time(e1) / reps
+                diff = float((lamh - lam).abs().max() / lam.abs().max())
+                key = "mg_pcg" if kry else "multigrid"
+                half[key] = {"value": round(N / msh / 1e3, 2), "ms_per_step": round(msh, 3),
+                             "cycles": ih["cycles"], "refinements": ih["outer_steps"],
+                             "rel_residual": ih["rel_residual"],
+                             "rel_divergence": ih["rel_divergence"], "setup_s": round(sh, 2),
+                             "lambda_rel_diff_vs_fp32_stencils": diff}
+                log(f"fp16 stencils, {key}: {msh:.1f} ms/step, {ih['cycles']} cycles, "
+                    f"{ih['outer_steps']} refinements, rel res {ih['rel_residual']:.2e}, "
+                    f"lambda diff {diff:.2e}")
+                del gh
+                torch.cuda.empty_cache()
         fp64 = None
         if not args.no_fp64:
             t0 = time.perf_counter()
@@ -596,6 +633,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "mg_pcg": krylov,
+        "fp16_stencils": half,
         "adjoint": adjoint,
         "coupling": coupling,
         "fp64_plain": fp64,

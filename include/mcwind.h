@@ -123,6 +123,13 @@ typedef struct {
                                  column top-down), restarted at every refinement step;
                                  needs nu_pre == nu_post */
   int32_t smoother;           /* mcw_smoother; default MCW_SMOOTH_POINT */
+  int32_t stencil_fp16;       /* FP32_REFINE only.  0 (default): the V-cycle's stencils are FP32.
+                                 1: they are kept in FP16 (52 instead of 104 bytes per node), each
+                                 level's off-diagonals divided by a power of two above their
+                                 largest magnitude; the V-cycle still computes in FP32 and the
+                                 refinement in FP64, so the solution meets rtol as before.  One
+                                 refinement step then reduces the residual by at most about 1e-3
+                                 (3e-5 with FP32 stencils).  Not part of the paper's method. */
 } mcw_options;
 
 #define MCW_MAX_LEVELS 24

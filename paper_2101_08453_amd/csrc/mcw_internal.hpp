@@ -110,6 +110,30 @@ __host__ __device__ inline size_t st_entry<float>(size_t p, int o) {
                 : base + 1536 + (p & 63) * 2 + (s - 24);
 }
 
+// FP16 stencils (option stencil_fp16): the same 26 off-diagonal coefficients,
+// divided by a power of two s per level (the level's largest magnitude rounded
+// up) and rounded once to FP16 (below 2^-14 to zero).  Per 64 consecutive nodes: three
+// groups of eight halves (slots 0-23) and one of two (slots 24, 25); 52 B per
+// node.  The kernels compute with the scaled values and scale f and r by 1/s
+// and s, both exact.
+constexpr int SW16 = 26;
+__host__ __device__ inline size_t st_entry16(size_t p, int o) {
+  const int s = slot32(o);
+  const size_t base = (p >> 6) * (size_t)(64 * SW16);
+  return s < 24 ? base + (size_t)(s >> 3) * 512 + (p & 63) * 8 + (s & 7)
+                : base + 1536 + (p & 63) * 2 + (s - 24);
+}
+
+// A level's stencil as the kernels see it: the array, whether it holds FP16
+// values, and the level scale s with its inverse (1 for FP32 and FP64).
+struct StRef {
+  const void* p = nullptr;
+  int h16 = 0;
+  float sc = 1.f, isc = 1.f;
+  StRef() = default;
+  StRef(const void* q) : p(q) {}  // NOLINT: an FP32 or FP64 array
+};
+
 // Diagonal of the FP32 operator from its off-diagonal coefficients a[o],
 // o != 13: minus their sum, accumulated in FP64 in the order of o and rounded
 // once, so that constants stay in the null space of the unconstrained FP32
@@ -188,6 +212,8 @@ struct ColJob {  // smoother colour pass, residual
   int by;                // rows of 64-column tiles per block (block = 64 * by threads)
   int tiles_x, nblocks;  // local grid of 64 x by column tiles
   double* part;          // per-block partial sums of a batched residual with a dot product
+  int h16;               // the stencil holds FP16 values scaled by 1/sc (FP32 V-cycles only)
+  float sc, isc;         // sc and 1/sc; 1 for FP32 and FP64 stencils
 };
 
 struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
@@ -282,7 +308,9 @@ struct Level {
   std::vector<int> keep_z;  // kept planes towards the next level (empty at the coarsest)
   int coarsen_h = 0;
   DevBuf st64;              // SW x N FP64 stencil (node-major, rows split even/odd in x)
-  DevBuf st32;              // SW x N FP32 stencil (FP32_REFINE), same layout
+  DevBuf st32;              // SW32 x N FP32 stencil (FP32_REFINE)
+  DevBuf st16;              // SW16 x N FP16 stencil (FP32_REFINE with stencil_fp16), scaled by 1/st_scale
+  float st_scale = 1.f;
   DevBuf x, f, r;           // level vectors in V-cycle precision, row-split order
   DirMap mx, my, mz;        // to the next coarser level
   DevBuf maps;              // device copies of the three DirMaps
@@ -366,7 +394,7 @@ void launch_recover_batched(const WorkList& W, hipStream_t s);
 // line_buf: null for the point smoother; for the vertical line smoother a
 // level-sized scratch vector (the elimination coefficients)
 template <class T>
-void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
+void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
                          hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr);
 // preconditioned conjugate gradients; sc = device scalars {r.z, alpha, beta, r.r}
 void launch_cg_reset(double* sc, hipStream_t s);
@@ -382,10 +410,10 @@ template <class T>
 void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, double* partials,
                       size_t cap, hipStream_t s);
 template <class T>
-void launch_neg_apply_dot(const Dims& d, const Faces& fc, const T* st, const T* p, T* q,
+void launch_neg_apply_dot(const Dims& d, const Faces& fc, StRef st, const T* p, T* q,
                           double* partials, size_t cap, size_t* n_part, hipStream_t s, int by);
 template <class T>
-void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
+void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
                      double* partials, size_t* n_part, hipStream_t s, int by = 4, size_t cap = 0);
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
@@ -402,7 +430,14 @@ void launch_fill(T* p, size_t n, T v, hipStream_t s);
 void launch_rap(const Dims& df, const Dims& dc, const DirMapDev& mx, const DirMapDev& my,
                 const DirMapDev& mz, const double* stf, double* stc, hipStream_t s);
 void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStream_t s);
-void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double, hipStream_t s);
+// largest |off-diagonal coefficient| of an FP64 stencil (device work, result on the host)
+double stencil_absmax(const Dims& d, const double* st64, double* scratch, hipStream_t s);
+// FP16 copy of an FP64 stencil's off-diagonals, each divided by scale (a power of two)
+void launch_round_stencil16(const Dims& d, const double* st64, uint16_t* st16, double inv_scale,
+                            hipStream_t s);
+// natural-order (27, N) copy: kind 0 FP32, 1 FP64, 2 FP16 times scale (written as FP32)
+void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int kind, hipStream_t s,
+                            float scale = 1.f);
 // r32 (row-split) = (float)(r * *scale); lam += e (row-split) / *scale (device scalar)
 void launch_scale_to_f32(const Dims& d, const double* r, const double* scale, float* r32,
                          hipStream_t s);
@@ -417,7 +452,7 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
                          hipStream_t s);
 
 // Job builders (colour = -1: all columns)
-ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
+ColJob col_job(const Dims& d, const Faces& fc, StRef st, const void* f, void* x, void* r,
                int colour, int by = 4);
 XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                  const DirMapDev& my, const DirMapDev& mz, const void* src, void* dst,

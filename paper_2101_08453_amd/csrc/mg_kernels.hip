@@ -72,6 +72,55 @@ __device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, s
 template <class T>
 __device__ __forceinline__ T load_nt(const T* p) { return __builtin_nontemporal_load(p); }
 
+// FP16 stencils: the 26 scaled off-diagonals as FP32 into a[o], o != 13, and
+// the diagonal formed from them as for FP32 stencils.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st, size_t p, float a[SW]) {
+  const _Float16* base = st + (p >> 6) * (size_t)(64 * SW16);
+  const f16x8* v = reinterpret_cast<const f16x8*>(base) + (p & 63);
+  float b[SW16];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const f16x8 t = __builtin_nontemporal_load(v + g * 64);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[8 * g + e] = (float)t[e];
+  }
+  const f16x2 t = __builtin_nontemporal_load(reinterpret_cast<const f16x2*>(base + 1536) + (p & 63));
+  b[24] = (float)t.x;
+  b[25] = (float)t.y;
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+    if (o != 13) a[o] = b[slot32(o)];
+  a[13] = stencil_diag(a);
+}
+
+// Stencil formats of a kernel instance: SF 0 holds T values (no scaling), SF 1
+// FP16 values scaled by 1/sc, SF 2 either, as each job says (batched kernels,
+// whose members may differ).  Single-grid launches pick 0 or 1, so an FP32 or
+// FP64 kernel carries no FP16 code.
+template <class T, int SF>
+__device__ __forceinline__ void load_stencil(const ColJob& J, size_t p, T a[SW]) {
+  if constexpr (sizeof(T) == 4 && SF == 1) {
+    load_stencil_h16(static_cast<const _Float16*>(J.st), p, a);
+    return;
+  }
+  if constexpr (sizeof(T) == 4 && SF == 2) {
+    if (J.h16) {
+      load_stencil_h16(static_cast<const _Float16*>(J.st), p, a);
+      return;
+    }
+  }
+  load_stencil_nt(static_cast<const T*>(J.st), p, a);
+}
+
+// v times the job's scale factor s, except for format 0 (T stencils, s = 1)
+template <int SF, class T>
+__device__ __forceinline__ T scaled(T v, float s) {
+  if constexpr (SF == 0) return v;
+  else return v * (T)s;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so that neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_remap(int b, int n) {
@@ -117,9 +166,8 @@ __device__ __forceinline__ void block_sum_to(double v, double* s_red, double* ou
 // top, or top to bottom for the reverse (adjoint) sweep.  Neighbour columns
 // belong to other colours and are not changed meanwhile; the value below (or
 // above) is this thread's own freshly updated one.
-template <class T, bool REV>
+template <class T, bool REV, int SF = 0>
 __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
-  const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
@@ -151,8 +199,8 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) xn[q] = x[(size_t)ka * plane + cols[q]];
     T a[SW];
-    load_stencil_nt(st, L.node(i, j, k), a);
-    T s = load_nt(f + (size_t)k * plane + cols[4]);
+    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    T s = scaled<SF>(load_nt(f + (size_t)k * plane + cols[4]), J.isc);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       if (o == 13) continue;
@@ -182,9 +230,8 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
 // and the modified right-hand sides in x, back substitution from the top
 // finishes x.  The solve is exact in the column, so a reverse sweep differs
 // from a forward one only in the order of the colours.
-template <class T>
+template <class T, int SF = 0>
 __device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
-  const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   T* __restrict__ cb = static_cast<T*>(J.r);
@@ -215,8 +262,8 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) xa[q] = x[(size_t)ka * plane + cols[q]];
     T a[SW];
-    load_stencil_nt(st, L.node(i, j, k), a);
-    T s = load_nt(f + (size_t)k * plane + cols[4]);
+    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    T s = scaled<SF>(load_nt(f + (size_t)k * plane + cols[4]), J.isc);
     const bool first = k == kf, last = k == kl;
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
@@ -251,20 +298,20 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
   }
 }
 
-template <class T, bool REV, bool LINE>
+template <class T, bool REV, bool LINE, int SF = 0>
 __device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j) {
-  if (LINE) line_column<T>(J, i, j);
-  else gs_column<T, REV>(J, i, j);
+  if (LINE) line_column<T, SF>(J, i, j);
+  else gs_column<T, REV, SF>(J, i, j);
 }
 
 // One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
 // tiles of 64 x J.by columns per block.
-template <class T, bool REV = false, bool LINE = false>
+template <class T, bool REV = false, bool LINE = false, int SF = 0>
 __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
   const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
   const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   if (ii >= J.ncx || jj >= J.ncy) return;
-  smooth_column<T, REV, LINE>(J, 2 * ii + J.ci, 2 * jj + J.cj);
+  smooth_column<T, REV, LINE, SF>(J, 2 * ii + J.ci, 2 * jj + J.cj);
 }
 
 // Two colour passes of the same rows in one launch: colour J0 then colour J1
@@ -279,25 +326,25 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
 template <class T, bool LINE>
 constexpr int fused_threads() { return sizeof(T) == 8 && LINE ? 512 : 1024; }
 
-template <class T, bool REV, bool LINE>
+template <class T, bool REV, bool LINE, int SF>
 __global__ __launch_bounds__((fused_threads<T, LINE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
   const int j = 2 * (int)blockIdx.x + J0.cj;
   for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
-    smooth_column<T, REV, LINE>(J0, 2 * ii + J0.ci, j);
+    smooth_column<T, REV, LINE, SF>(J0, 2 * ii + J0.ci, j);
   __syncthreads();
   for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
-    smooth_column<T, REV, LINE>(J1, 2 * ii + J1.ci, j);
+    smooth_column<T, REV, LINE, SF>(J1, 2 * ii + J1.ci, j);
 }
 
-template <class T, bool REV, bool LINE>
+template <class T, bool REV, bool LINE, int SF>
 __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
-  gs_pass_body<T, REV, LINE>(J, xcd_remap(blockIdx.x, J.nblocks));
+  gs_pass_body<T, REV, LINE, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
 }
 
 template <class T>
-__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false>(J, b); }
+__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false, 2>(J, b); }
 template <class T>
-__device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false>(J, b); }
+__device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false, 2>(J, b); }
 
 template <class T>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
@@ -313,9 +360,8 @@ __global__ __launch_bounds__(256) void gs_pass_batched_rev(WorkList W) {
 
 // r = f - K x at free nodes (f null: r = -K x), 0 at fixed nodes; returns this
 // thread's sum of r^2, or of x r with DOTX.
-template <class T, bool DOTX = false>
+template <class T, bool DOTX = false, int SF = 0>
 __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
-  const T* __restrict__ st = static_cast<const T*>(J.st);
   const T* __restrict__ x = static_cast<const T*>(J.x);
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ r = static_cast<T*>(J.r);
@@ -353,15 +399,15 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
     T a[SW];
-    load_stencil_nt(st, L.node(i, j, k), a);
-    T s = f ? load_nt(f + (size_t)k * plane + own) : T(0);
+    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    T s = f ? scaled<SF>(load_nt(f + (size_t)k * plane + own), J.isc) : T(0);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
       const int dk = o / 9, q = o % 9;
       const T xv = dk == 0 ? xm[q] : (dk == 1 ? x0[q] : xp[q]);
       s -= a[o] * xv;
     }
-    const T res = (k >= kf && k <= kl) ? s : T(0);
+    const T res = (k >= kf && k <= kl) ? scaled<SF>(s, J.sc) : T(0);
     r[(size_t)k * plane + own] = res;
     acc += (double)(DOTX ? x0[4] : res) * (double)res;
 #pragma unroll
@@ -373,10 +419,10 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   return acc;
 }
 
-template <class T, bool NORM, bool DOTX = false>
+template <class T, bool NORM, bool DOTX, int SF>
 __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restrict__ partials) {
   __shared__ double s_red[256];
-  const double acc = residual_body<T, DOTX>(J, xcd_remap(blockIdx.x, J.nblocks));
+  const double acc = residual_body<T, DOTX, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
   if (NORM) {
     // blocks narrower than 256 threads: the missing lanes add zero
     if (threadIdx.x == 0)
@@ -386,13 +432,13 @@ __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restr
 }
 
 template <class T>
-__device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T>(J, b); }
+__device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T, false, 2>(J, b); }
 
-// q = -K p with p.q per block, as residual_kernel<T, true, true> does for block b
+// q = -K p with p.q per block, as residual_kernel<T, true, true, SF> does for block b
 template <class T>
 __device__ __forceinline__ void residual_dot_item(const ColJob& J, int b) {
   __shared__ double s_red[256];
-  const double acc = residual_body<T, true>(J, xcd_remap(b, J.nblocks));
+  const double acc = residual_body<T, true, 2>(J, xcd_remap(b, J.nblocks));
   if (threadIdx.x == 0)
     for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
   block_sum_to(acc, s_red, &J.part[b]);
@@ -772,6 +818,81 @@ __global__ __launch_bounds__(256) void round_stencil_kernel(const double* __rest
     if (o != 13) s32[st_entry<float>(p, o)] = (float)s64[st_entry<double>(p, o)];
 }
 
+// FP16 copy: each off-diagonal divided by the level scale (exact) and rounded
+// once, from FP64, to the nearest FP16 value; values below the smallest normal
+// FP16 number (2^-14, i.e. below 2^-14 of the level's scale) are stored as zero.
+// This is the definition the tests check; it does not depend on how the
+// hardware treats FP16 subnormals.
+__global__ __launch_bounds__(256) void round_stencil16_kernel(const double* __restrict__ s64,
+                                                              _Float16* __restrict__ s16, int NX,
+                                                              int NY, size_t N, double inv_scale) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const StLayout L = dev_layout(NX, NY);
+  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+    if (o != 13) {
+      const double v = s64[st_entry<double>(p, o)] * inv_scale;
+      s16[st_entry16(p, o)] = fabs(v) < 0x1p-14 ? (_Float16)0.0 : (_Float16)v;
+    }
+}
+
+// Largest |off-diagonal| of an FP64 stencil: a per-block maximum (fixed tree),
+// then one block over the block maxima.
+__global__ __launch_bounds__(256) void absmax_kernel(const double* __restrict__ s64, int NX, int NY,
+                                                     size_t N, double* __restrict__ out) {
+  __shared__ double sm[256];
+  const StLayout L = dev_layout(NX, NY);
+  double m = 0.0;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+    for (int o = 0; o < 27; ++o)
+      if (o != 13) m = fmax(m, fabs(s64[st_entry<double>(p, o)]));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void max_of_kernel(const double* __restrict__ v, int n,
+                                                     double* __restrict__ out) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, v[t]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// FP16 stencil in natural order, as the FP32 values the kernels use times the scale
+__global__ __launch_bounds__(256) void unsplit16_kernel(const _Float16* __restrict__ s,
+                                                        float* __restrict__ out, int NX, int NY,
+                                                        size_t N, float scale) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= N * 27) return;
+  const size_t o = gid / N, n = gid % N;
+  const StLayout L = dev_layout(NX, NY);
+  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+  if (o == 13) {
+    float a[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) a[q] = q == 13 ? 0.f : (float)s[st_entry16(p, q)];
+    out[gid] = stencil_diag(a) * scale;
+  } else {
+    out[gid] = (float)s[st_entry16(p, (int)o)] * scale;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T* __restrict__ out,
                                                       int NX, int NY, size_t N) {
@@ -957,11 +1078,14 @@ unsigned batched_grid(int total) { return (unsigned)std::max(1, std::min(total, 
 
 // ---------------------------------------------------------------- job builders
 
-ColJob col_job(const Dims& d, const Faces& fc, const void* st, const void* f, void* x, void* r,
+ColJob col_job(const Dims& d, const Faces& fc, StRef st, const void* f, void* x, void* r,
                int colour, int by) {
   ColJob J{};
   J.by = by;
-  J.st = st;
+  J.st = st.p;
+  J.h16 = st.h16;
+  J.sc = st.sc;
+  J.isc = st.isc;
   J.f = f;
   J.x = x;
   J.r = r;
@@ -1024,8 +1148,8 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 
 // ---------------------------------------------------------------- single launches
 
-template <class T, bool LINE>
-void smooth_sweep_t(const Dims& d, const Faces& fc, const T* st, const T* f, T* x, T* cbuf,
+template <class T, bool LINE, int SF>
+void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
                     hipStream_t s, int by, bool reverse) {
   if (by == 0) {
     // colours (0,0),(1,0) then (0,1),(1,1); reversed: (1,1),(0,1) then (1,0),(0,0)
@@ -1037,9 +1161,9 @@ void smooth_sweep_t(const Dims& d, const Faces& fc, const T* st, const T* f, T* 
       const int cols = std::max(J0.ncx, J1.ncx);
       const int threads = std::min(fused_threads<T, LINE>(), std::max(64, (cols + 63) / 64 * 64));
       if (reverse)
-        gs_fused_kernel<T, true, LINE><<<J0.ncy, threads, 0, s>>>(J0, J1);
+        gs_fused_kernel<T, true, LINE, SF><<<J0.ncy, threads, 0, s>>>(J0, J1);
       else
-        gs_fused_kernel<T, false, LINE><<<J0.ncy, threads, 0, s>>>(J0, J1);
+        gs_fused_kernel<T, false, LINE, SF><<<J0.ncy, threads, 0, s>>>(J0, J1);
       MCW_CHECK_LAUNCH();
     }
     return;
@@ -1049,15 +1173,28 @@ void smooth_sweep_t(const Dims& d, const Faces& fc, const T* st, const T* f, T* 
     const ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
     if (J.nblocks <= 0) continue;
     if (reverse)
-      gs_pass_kernel<T, true, LINE><<<J.nblocks, BX * by, 0, s>>>(J);
+      gs_pass_kernel<T, true, LINE, SF><<<J.nblocks, BX * by, 0, s>>>(J);
     else
-      gs_pass_kernel<T, false, LINE><<<J.nblocks, BX * by, 0, s>>>(J);
+      gs_pass_kernel<T, false, LINE, SF><<<J.nblocks, BX * by, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
 }
 
+// format 1 (FP16 stencil) exists for FP32 V-cycles only
+template <class T, bool LINE>
+void smooth_sweep_t(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
+                    hipStream_t s, int by, bool reverse) {
+  if constexpr (sizeof(T) == 4) {
+    if (st.h16) {
+      smooth_sweep_f<T, LINE, 1>(d, fc, st, f, x, cbuf, s, by, reverse);
+      return;
+    }
+  }
+  smooth_sweep_f<T, LINE, 0>(d, fc, st, f, x, cbuf, s, by, reverse);
+}
+
 template <class T>
-void launch_smooth_sweep(const Dims& d, const Faces& fc, const T* st, const T* f, T* x,
+void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
                          hipStream_t s, int by, bool reverse, T* line_buf) {
   if (line_buf)
     smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse);
@@ -1289,25 +1426,33 @@ void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, 
 }
 
 template <class T>
-void launch_residual(const Dims& d, const Faces& fc, const T* st, const T* x, const T* f, T* r,
+void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
                      double* partials, size_t* n_part, hipStream_t s, int by, size_t cap) {
   const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
   if (partials) need_partials((size_t)J.nblocks, cap);
-  if (partials)
-    residual_kernel<T, true><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  const bool h16 = sizeof(T) == 4 && st.h16;
+  if (partials && h16)
+    residual_kernel<T, true, false, 1><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  else if (partials)
+    residual_kernel<T, true, false, 0><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  else if (h16)
+    residual_kernel<T, false, false, 1><<<J.nblocks, BX * by, 0, s>>>(J, nullptr);
   else
-    residual_kernel<T, false><<<J.nblocks, BX * by, 0, s>>>(J, nullptr);
+    residual_kernel<T, false, false, 0><<<J.nblocks, BX * by, 0, s>>>(J, nullptr);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = J.nblocks;
 }
 
 // q = -K p with the per-block partial sums of p.q
 template <class T>
-void launch_neg_apply_dot(const Dims& d, const Faces& fc, const T* st, const T* p, T* q,
+void launch_neg_apply_dot(const Dims& d, const Faces& fc, StRef st, const T* p, T* q,
                           double* partials, size_t cap, size_t* n_part, hipStream_t s, int by) {
   const ColJob J = col_job(d, fc, st, nullptr, const_cast<T*>(p), q, -1, by);
   need_partials((size_t)J.nblocks, cap);
-  residual_kernel<T, true, true><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  if (sizeof(T) == 4 && st.h16)
+    residual_kernel<T, true, true, 1><<<J.nblocks, BX * by, 0, s>>>(J, partials);
+  else
+    residual_kernel<T, true, true, 0><<<J.nblocks, BX * by, 0, s>>>(J, partials);
   MCW_CHECK_LAUNCH();
   *n_part = J.nblocks;
 }
@@ -1367,17 +1512,41 @@ void launch_round_stencil(const Dims& d, const double* st64, float* st32, hipStr
   MCW_CHECK_LAUNCH();
 }
 
-void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int is_double,
-                            hipStream_t s) {
+void launch_unsplit_stencil(const Dims& d, const void* st, void* out, int kind, hipStream_t s,
+                            float scale) {
   const size_t N = d.N();
   const unsigned blocks = (unsigned)((N * 27 + 255) / 256);
-  if (is_double)
+  if (kind == 1)
     unsplit_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(st),
                                                   static_cast<double*>(out), d.NX(), d.NY(), N);
+  else if (kind == 2)
+    unsplit16_kernel<<<blocks, 256, 0, s>>>(static_cast<const _Float16*>(st),
+                                            static_cast<float*>(out), d.NX(), d.NY(), N, scale);
   else
     unsplit_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(st),
                                                  static_cast<float*>(out), d.NX(), d.NY(), N);
   MCW_CHECK_LAUNCH();
+}
+
+void launch_round_stencil16(const Dims& d, const double* st64, uint16_t* st16, double inv_scale,
+                            hipStream_t s) {
+  const size_t N = d.N();
+  round_stencil16_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
+      st64, reinterpret_cast<_Float16*>(st16), d.NX(), d.NY(), N, inv_scale);
+  MCW_CHECK_LAUNCH();
+}
+
+double stencil_absmax(const Dims& d, const double* st64, double* scratch, hipStream_t s) {
+  const size_t N = d.N();
+  const int blocks = (int)std::min<size_t>((N + 255) / 256, 1024);
+  absmax_kernel<<<blocks, 256, 0, s>>>(st64, d.NX(), d.NY(), N, scratch);
+  MCW_CHECK_LAUNCH();
+  max_of_kernel<<<1, 256, 0, s>>>(scratch, blocks, scratch + blocks);
+  MCW_CHECK_LAUNCH();
+  double m = 0.0;
+  MCW_HIP(hipMemcpyAsync(&m, scratch + blocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  MCW_HIP(hipStreamSynchronize(s));
+  return m;
 }
 
 template <class T>
@@ -1539,7 +1708,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 }
 
 #define MCW_INST(T)                                                                             \
-  template void launch_smooth_sweep<T>(const Dims&, const Faces&, const T*, const T*, T*,       \
+  template void launch_smooth_sweep<T>(const Dims&, const Faces&, StRef, const T*, T*,          \
                                        hipStream_t, int, bool, T*);                             \
   template void launch_cg_beta<T>(const T*, const T*, const T*, size_t, double*, size_t,       \
                                   double*, hipStream_t);                                        \
@@ -1547,9 +1716,9 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_cg_direction<T>(T*, const T*, const double*, size_t, hipStream_t);       \
   template void launch_cg_update<T>(T*, const T*, T*, const T*, double*, size_t, double*,      \
                                     size_t, hipStream_t);                                       \
-  template void launch_neg_apply_dot<T>(const Dims&, const Faces&, const T*, const T*, T*,      \
+  template void launch_neg_apply_dot<T>(const Dims&, const Faces&, StRef, const T*, T*,         \
                                         double*, size_t, size_t*, hipStream_t, int);            \
-  template void launch_residual<T>(const Dims&, const Faces&, const T*, const T*, const T*, T*, \
+  template void launch_residual<T>(const Dims&, const Faces&, StRef, const T*, const T*, T*,    \
                                    double*, size_t*, hipStream_t, int, size_t);                 \
   template void launch_restrict<T>(const Dims&, const Dims&, const Faces&, const DirMapDev&,    \
                                    const DirMapDev&, const DirMapDev&, const T*, T*,            \

@@ -303,9 +303,18 @@ void reduce_to_host(mcw_handle& h, size_t n_part, int width, double* out) {
 
 // ---------------------------------------------------------------- V-cycle
 
-template <class T> const T* stencil_of(const Level& L);
-template <> const double* stencil_of<double>(const Level& L) { return L.st64.as<double>(); }
-template <> const float* stencil_of<float>(const Level& L) { return L.st32.as<float>(); }
+// The stencil the V-cycle of precision T uses on level L: FP64, FP32, or FP16
+// scaled by 1/st_scale (option stencil_fp16).
+template <class T> StRef stencil_of(const Level& L);
+template <> StRef stencil_of<double>(const Level& L) { return StRef(L.st64.p); }
+template <> StRef stencil_of<float>(const Level& L) {
+  if (!L.st16.p) return StRef(L.st32.p);
+  StRef r(L.st16.p);
+  r.h16 = 1;
+  r.sc = L.st_scale;
+  r.isc = 1.f / L.st_scale;
+  return r;
+}
 
 // Scratch of the vertical line smoother (the level's residual vector, idle
 // while smoothing), or null for the point smoother.
@@ -324,7 +333,7 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
                              h.stream);
     return;
   }
-  const T* st = stencil_of<T>(L);
+  const StRef st = stencil_of<T>(L);
   for (int s = 0; s < h.opt.nu_pre; ++s)
     launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L));
   launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res);
@@ -438,6 +447,13 @@ int pcg_inner(mcw_handle& h, const Krylov<T>& v, int m_max, double rr_stop) {
 // 0.55), so that a slow solve needs no extra FP64 residual evaluations.
 constexpr int kMaxInnerCycles = 20;
 
+// The smallest reduction of the true residual one refinement step is asked for:
+// what the V-cycle's operator resolves.  FP32 stencils: 3e-5.  FP16 stencils
+// perturb the operator by about 1e-4 relative per coefficient, and one step
+// then reduces the FP64 residual by about 1e-3 at best, however many V-cycles
+// it runs (measured with the oracle's multigrid on a 64x64x15 fractal grid).
+double inner_floor(const mcw_handle& h) { return h.opt.stencil_fp16 ? 1e-3 : 3e-5; }
+
 int inner_steps(double target, double rho, int cap) {
   const int m = (int)std::ceil(std::log(target) / std::log(rho));
   return std::max(1, std::min(m, cap));
@@ -533,7 +549,7 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     // residual for an extra V-cycle, which costs about four times as much.)
     int m = h.opt.inner_cycles > 0
                 ? h.opt.inner_cycles
-                : inner_steps(std::max(tol / pg.rel, 3e-5), rho_est, kMaxInnerCycles);
+                : inner_steps(std::max(tol / pg.rel, inner_floor(h)), rho_est, kMaxInnerCycles);
     m = std::min(m, h.opt.max_cycles - pg.cycles);
     // scale the residual by a power of two to O(1) before rounding it to FP32
     const double rms = std::sqrt(rr / nfree);
@@ -545,7 +561,7 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     if (h.opt.krylov) {
       // until the scaled FP32 residual has dropped by the same target as above
       const Krylov<float> kv = krylov_vecs<float>(h);
-      const double target = std::max(tol / pg.rel, 3e-5);
+      const double target = std::max(tol / pg.rel, inner_floor(h));
       const double r0 = std::sqrt(rr) * h.host_scalars[7];
       const int m_max = std::min(h.opt.inner_cycles > 0 ? h.opt.inner_cycles : 30,
                                  h.opt.max_cycles - pg.cycles);
@@ -700,7 +716,8 @@ void autotune_levels(mcw_handle& h) {
   for (auto& L : h.levels) {
     if (L.d.N() < (size_t)1 << 16) continue;
     const std::string dims = std::to_string(L.d.NX()) + "x" + std::to_string(L.d.NY()) + "x" +
-                             std::to_string(L.d.NZ()) + (sizeof(T) == 4 ? "|f32" : "|f64");
+                             std::to_string(L.d.NZ()) +
+                             (sizeof(T) == 8 ? "|f64" : (L.st16.p ? "|h16" : "|f32"));
     int v = 0;
     const std::string gs_key = arch + (h.opt.smoother == MCW_SMOOTH_LINE ? "|gsl|" : "|gsf|") + dims;
     const bool have_gs = cache.get(gs_key, v);
@@ -710,7 +727,7 @@ void autotune_levels(mcw_handle& h) {
     if (have_gs && have_res) continue;
     launch_fill<T>(L.f.as<T>(), L.d.N(), T(0), h.stream);
     launch_fill<T>(L.x.as<T>(), L.d.N(), T(0), h.stream);
-    const T* st = stencil_of<T>(L);
+    const StRef st = stencil_of<T>(L);
     for (int which = 0; which < 2; ++which) {
       if ((which == 0 && have_gs) || (which == 1 && have_res)) continue;
       float best = 1e30f;
@@ -772,6 +789,9 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
   if (o.krylov != 0 && o.krylov != 1) Fail::arg("krylov must be 0 or 1");
   if (o.krylov && o.nu_pre != o.nu_post) Fail::arg("krylov needs nu_pre == nu_post (a symmetric V-cycle)");
   if (o.smoother != MCW_SMOOTH_POINT && o.smoother != MCW_SMOOTH_LINE) Fail::arg("bad smoother");
+  if (o.stencil_fp16 != 0 && o.stencil_fp16 != 1) Fail::arg("stencil_fp16 must be 0 or 1");
+  if (o.stencil_fp16 && o.precision != MCW_FP32_REFINE)
+    Fail::arg("stencil_fp16 needs precision FP32_REFINE");
 }
 
 void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, mcw_handle& h) {
@@ -873,9 +893,20 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
       C.st64.alloc(SW * C.d.layout().nodes * sizeof(double));
       launch_rap(L.d, C.d, L.dmx, L.dmy, L.dmz, L.st64.as<double>(), C.st64.as<double>(), h.stream);
     }
-    if (f32) {
+    if (f32 && opt.stencil_fp16) {
+      // FP16 off-diagonals divided by a power of two at least the level's largest magnitude
+      DevBuf scratch;
+      scratch.alloc(1025 * sizeof(double));
+      const double amax = stencil_absmax(L.d, L.st64.as<double>(), scratch.as<double>(), h.stream);
+      const double scale = amax > 0.0 ? std::ldexp(1.0, std::ilogb(amax) + 1) : 1.0;
+      L.st_scale = (float)scale;
+      L.st16.alloc(SW16 * L.d.layout().nodes * sizeof(uint16_t));
+      launch_round_stencil16(L.d, L.st64.as<double>(), L.st16.as<uint16_t>(), 1.0 / scale, h.stream);
+    } else if (f32) {
       L.st32.alloc(SW32 * L.d.layout().nodes * sizeof(float));
       launch_round_stencil(L.d, L.st64.as<double>(), L.st32.as<float>(), h.stream);
+    }
+    if (f32) {
       if (l + 1 < h.levels.size()) {
         MCW_HIP(hipStreamSynchronize(h.stream));
         L.st64.release();
@@ -1106,13 +1137,13 @@ class Batch {
         }
         Level& C = h.levels[d + 1];
         for (int c = 0; c < 4; ++c) {
-          const ColJob J = col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, nullptr, c, by_gs_[d]);
+          const ColJob J = col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, nullptr, c, by_gs_[d]);
           if (J.nblocks > 0) {
             gsj[c].push_back(J);
             gsm[c].push_back(i);
           }
         }
-        rj.push_back(col_job(V.d, h.faces, V.st32.p, V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
+        rj.push_back(col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
         rm.push_back(i);
         rsj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, V.r.p, C.f.p, true));
         rsm.push_back(i);
@@ -1210,7 +1241,7 @@ class Batch {
       mcw_handle& h = *hs_[i];
       Level& V = h.levels[0];
       const size_t N = V.d.N();
-      ColJob J = col_job(V.d, h.faces, V.st32.p, nullptr, h.kp.p, h.kq.p, -1, by_res_[0]);
+      ColJob J = col_job(V.d, h.faces, stencil_of<float>(V), nullptr, h.kp.p, h.kq.p, -1, by_res_[0]);
       J.part = h.partials.as<double>();
       need_partials((size_t)J.nblocks, h.n_partials);
       need_partials(2 * (size_t)cg_blocks(N), h.n_partials);
@@ -1325,7 +1356,7 @@ class Batch {
         if (!S.active) continue;
         int mi = h.opt.inner_cycles;
         if (mi <= 0) {
-          mi = inner_steps(std::max(tol / S.rel, 3e-5), S.rho_est, kMaxInnerCycles);
+          mi = inner_steps(std::max(tol / S.rel, inner_floor(h)), S.rho_est, kMaxInnerCycles);
         }
         mi = std::min(mi, h.opt.max_cycles - S.cycles);
         want = std::max(want, mi);
@@ -1334,7 +1365,7 @@ class Batch {
         reinterpret_cast<double*>(&host_[scales_slot_])[i] = scale;
         // CG stops on its own residual: the same target, in the scaled FP32 units
         cg_mmax[i] = std::min(h.opt.inner_cycles > 0 ? h.opt.inner_cycles : 30, h.opt.max_cycles - S.cycles);
-        const double stop = h.opt.inner_cycles > 0 ? 0.0 : std::max(tol / S.rel, 3e-5) * std::sqrt(rr) * scale;
+        const double stop = h.opt.inner_cycles > 0 ? 0.0 : std::max(tol / S.rel, inner_floor(h)) * std::sqrt(rr) * scale;
         cg_stop2[i] = stop * stop;
       }
       for (int i = 0; i < m_; ++i) act[i] = ms[i].active ? 1 : 0;
@@ -1678,6 +1709,7 @@ void mcw_default_options(mcw_options* o) {
   o->autotune = 1;
   o->krylov = 0;
   o->smoother = MCW_SMOOTH_POINT;
+  o->stencil_fp16 = 0;
 }
 
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,
@@ -1897,8 +1929,10 @@ mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out) {
         Fail::arg("FP64 coarse stencils are kept only by FP64 handles");
       }
     } else if (prec == MCW_FP32_REFINE) {
-      if (!L.st32.p) Fail::arg("FP32 stencils exist only in FP32_REFINE handles");
-      launch_unsplit_stencil(L.d, L.st32.p, out, 0, h->stream);
+      // the values the FP32 V-cycle computes with (FP16 ones times their level scale)
+      if (L.st16.p) launch_unsplit_stencil(L.d, L.st16.p, out, 2, h->stream, L.st_scale);
+      else if (L.st32.p) launch_unsplit_stencil(L.d, L.st32.p, out, 0, h->stream);
+      else Fail::arg("FP32 stencils exist only in FP32_REFINE handles");
     } else {
       Fail::arg("bad precision");
     }
@@ -1991,10 +2025,10 @@ mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps
       if (is_f32(h)) {
         float *x = L.x.as<float>(), *f = L.f.as<float>(), *rr = L.r.as<float>();
         if (kernel == 0)
-          launch_smooth_sweep<float>(L.d, h->faces, L.st32.as<float>(), f, x, h->stream, L.by_gs, false,
+          launch_smooth_sweep<float>(L.d, h->faces, stencil_of<float>(L), f, x, h->stream, L.by_gs, false,
                                      line_buf<float>(*h, L));
         if (kernel == 1)
-          launch_residual<float>(L.d, h->faces, L.st32.as<float>(), x, f, rr, nullptr, nullptr, h->stream,
+          launch_residual<float>(L.d, h->faces, stencil_of<float>(L), x, f, rr, nullptr, nullptr, h->stream,
                                  L.by_res);
         if (kernel == 2 || kernel == 3) {
           Level& C = h->levels[l + 1];

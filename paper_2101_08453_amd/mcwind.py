@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("coarsen_rule", ctypes.c_int32), ("coarse_direct_max", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("autotune", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("stencil_fp16", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -168,7 +169,7 @@ class Grid:
     def __init__(self, X, Y, Z, a, gamma=GAMMA_BOTTOM, precision="fp32_refine", rtol=1e-8,
                  max_cycles=200, nu_pre=2, nu_post=2, inner_cycles=0, coarsen_rule="operator",
                  coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True,
-                 krylov=False, smoother="point"):
+                 krylov=False, smoother="point", stencil_fp16=False):
         L = lib()
         self._h = H()
         nzp, nyp, nxp = X.shape
@@ -197,6 +198,7 @@ class Grid:
         o.autotune = 1 if autotune else 0
         o.krylov = 1 if krylov else 0
         o.smoother = SMOOTHERS[smoother]
+        o.stencil_fp16 = 1 if stencil_fp16 else 0
         o.verbose = 1 if (verbose or os.environ.get("MCW_LOG")) else 0
         self.precision = precision
         self.vdtype = torch.float32 if precision == "fp32_refine" else torch.float64

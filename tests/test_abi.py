@@ -47,6 +47,8 @@ def test_status_strings_and_defaults(lib):
     o = mcwind.default_options()
     assert o.precision == mcwind.FP32_REFINE and o.rtol == 1e-8
     assert (o.nu_pre, o.nu_post, o.coarsen_rule, o.use_graph) == (2, 2, 0, 1)
+    # the last fields: a layout mismatch with the header would read other values here
+    assert (o.krylov, o.smoother, o.stencil_fp16) == (0, 0, 0)
 
 
 def test_create_rejects_bad_arguments_on_the_host(lib):
@@ -69,6 +71,14 @@ def test_create_rejects_bad_arguments_on_the_host(lib):
     o = mcwind.default_options()
     d.gamma_faces = 1
     o.coarse_direct_max = 0
+    assert lib.mcw_create(ctypes.byref(d), ctypes.byref(o), None, ctypes.byref(h)) == 1
+    o = mcwind.default_options()
+    o.precision = mcwind.FP64
+    o.stencil_fp16 = 1  # FP16 stencils serve the FP32 V-cycle only
+    assert lib.mcw_create(ctypes.byref(d), ctypes.byref(o), None, ctypes.byref(h)) == 1
+    assert b"stencil_fp16" in lib.mcw_last_error(None)
+    o.precision = mcwind.FP32_REFINE
+    o.stencil_fp16 = 2
     assert lib.mcw_create(ctypes.byref(d), ctypes.byref(o), None, ctypes.byref(h)) == 1
     assert not h.value
 
