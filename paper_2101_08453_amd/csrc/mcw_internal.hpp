@@ -461,16 +461,18 @@ CoarseJob coarse_job(int n, const double* inv, const int* idx, const void* r, vo
 VecJob vec_job(void* p, const void* q, size_t n, const double* scale);
 
 // Batched (persistent) launches over a work list of jobs
-template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by = 4, bool reverse = false);
+// h16: every job of W has FP16 stencils (else none has); the batched colour
+// pass, residual and q = -K p run the kernel instance of that format
+template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16);
 // batched conjugate gradients (lists of CgJob; residual lists of ColJob with part set)
 unsigned cg_blocks(size_t n);
 template <class T> void launch_dot2_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_cg_direction_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_cg_update_batched(const WorkList& W, hipStream_t s);
-template <class T> void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by);
+template <class T> void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by, bool h16);
 void launch_cg_coeff_batched(const CgJob* jobs, int n, int mode, const int* active, hipStream_t s);
 void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStream_t s);
-template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by = 4);
+template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16);
 template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s);

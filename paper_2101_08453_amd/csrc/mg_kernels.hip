@@ -96,27 +96,25 @@ __device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st
 }
 
 // Stencil formats of a kernel instance: SF 0 holds T values (no scaling), SF 1
-// FP16 values scaled by 1/sc, SF 2 either, as each job says (batched kernels,
-// whose members may differ).  Single-grid launches pick 0 or 1, so an FP32 or
-// FP64 kernel carries no FP16 code.
+// FP16 values scaled by 1/sc.  Each launch, single or batched, runs the
+// instance of its stencils' format, so an FP32 or FP64 kernel carries no FP16
+// code (a format chosen per job at run time cost the batched FP32 kernels up
+// to 40 registers per lane).
 template <class T, int SF>
 __device__ __forceinline__ void load_stencil(const ColJob& J, size_t p, T a[SW]) {
-  if constexpr (sizeof(T) == 4 && SF == 1) {
+  if constexpr (sizeof(T) == 4 && SF == 1)
     load_stencil_h16(static_cast<const _Float16*>(J.st), p, a);
-    return;
-  }
-  if constexpr (sizeof(T) == 4 && SF == 2) {
-    if (J.h16) {
-      load_stencil_h16(static_cast<const _Float16*>(J.st), p, a);
-      return;
-    }
-  }
-  load_stencil_nt(static_cast<const T*>(J.st), p, a);
+  else
+    load_stencil_nt(static_cast<const T*>(J.st), p, a);
 }
 
-// v times the job's scale factor s, except for format 0 (T stencils, s = 1)
+// v times the job's scale factor s, except for format 0 (T stencils, s = 1).
+// s is a power of two, so the product is exact; it must not be contracted into
+// the FMA of the first stencil term, which would round that term's product on
+// its own and make a batched FP32 member (s = 1) differ from a single launch.
 template <int SF, class T>
 __device__ __forceinline__ T scaled(T v, float s) {
+#pragma clang fp contract(off)
   if constexpr (SF == 0) return v;
   else return v * (T)s;
 }
@@ -318,17 +316,18 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
 // on every row j = cj mod 2, one block per row.  The J1 columns of a row couple
 // only to the J0 columns of the same row (and to untouched rows j +- 1), so a
 // block barrier between the two halves keeps the order of the separate passes
-// and gives the same result bit for bit, while x of rows j-1, j, j+1 is
-// fetched once for both colours.
-// Threads per block of the fused pass: 1024, except the FP64 line smoother,
-// whose Thomas sweep needs more than the 128 registers a 1024-thread block
-// leaves per lane (it spilled); with 512 threads it has 256.
+// and gives the same result bit for bit, with one launch instead of two.
+// Each XCD takes a contiguous range of rows, so that the blocks of rows j and
+// j + 2 running there at the same time share row j + 1 in its L2.
+// Threads per block: 1024, except the FP64 line smoother, whose Thomas sweep
+// needs more than the 128 registers a 1024-thread block leaves per lane (it
+// spilled); with 512 threads it has 256.
 template <class T, bool LINE>
 constexpr int fused_threads() { return sizeof(T) == 8 && LINE ? 512 : 1024; }
 
 template <class T, bool REV, bool LINE, int SF>
 __global__ __launch_bounds__((fused_threads<T, LINE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
-  const int j = 2 * (int)blockIdx.x + J0.cj;
+  const int j = 2 * xcd_remap(blockIdx.x, gridDim.x) + J0.cj;
   for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
     smooth_column<T, REV, LINE, SF>(J0, 2 * ii + J0.ci, j);
   __syncthreads();
@@ -341,19 +340,19 @@ __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
   gs_pass_body<T, REV, LINE, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
 }
 
-template <class T>
-__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false, 2>(J, b); }
-template <class T>
-__device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false, 2>(J, b); }
+template <class T, int SF>
+__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false, SF>(J, b); }
+template <class T, int SF>
+__device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false, SF>(J, b); }
 
-template <class T>
+template <class T, int SF>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, gs_pass_fwd<T>)
+  MCW_BATCHED_LOOP(ColJob, (gs_pass_fwd<T, SF>))
 }
 
-template <class T>
+template <class T, int SF>
 __global__ __launch_bounds__(256) void gs_pass_batched_rev(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, gs_pass_rev<T>)
+  MCW_BATCHED_LOOP(ColJob, (gs_pass_rev<T, SF>))
 }
 
 // ---------------------------------------------------------------- residual
@@ -431,27 +430,27 @@ __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restr
   }
 }
 
-template <class T>
-__device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T, false, 2>(J, b); }
+template <class T, int SF>
+__device__ __forceinline__ void residual_nonorm(const ColJob& J, int b) { (void)residual_body<T, false, SF>(J, b); }
 
 // q = -K p with p.q per block, as residual_kernel<T, true, true, SF> does for block b
-template <class T>
+template <class T, int SF>
 __device__ __forceinline__ void residual_dot_item(const ColJob& J, int b) {
   __shared__ double s_red[256];
-  const double acc = residual_body<T, true, 2>(J, xcd_remap(b, J.nblocks));
+  const double acc = residual_body<T, true, SF>(J, xcd_remap(b, J.nblocks));
   if (threadIdx.x == 0)
     for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
   block_sum_to(acc, s_red, &J.part[b]);
 }
 
-template <class T>
+template <class T, int SF>
 __global__ __launch_bounds__(256) void residual_dot_batched(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, residual_dot_item<T>)
+  MCW_BATCHED_LOOP(ColJob, (residual_dot_item<T, SF>))
 }
 
-template <class T>
+template <class T, int SF>
 __global__ __launch_bounds__(256) void residual_batched(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, residual_nonorm<T>)
+  MCW_BATCHED_LOOP(ColJob, (residual_nonorm<T, SF>))
 }
 
 // ---------------------------------------------------------------- transfers
@@ -1597,14 +1596,25 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
 
 // ---------------------------------------------------------------- batched launches
 
-template <class T>
-void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse) {
-  if (W.total <= 0) return;
+template <class T, int SF>
+void launch_gs_batched_f(const WorkList& W, hipStream_t s, int by, bool reverse) {
   if (reverse)
-    gs_pass_batched_rev<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+    gs_pass_batched_rev<T, SF><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   else
-    gs_pass_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+    gs_pass_batched<T, SF><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16) {
+  if (W.total <= 0) return;
+  if constexpr (sizeof(T) == 4) {
+    if (h16) {
+      launch_gs_batched_f<T, 1>(W, s, by, reverse);
+      return;
+    }
+  }
+  launch_gs_batched_f<T, 0>(W, s, by, reverse);
 }
 
 template <class T>
@@ -1629,9 +1639,12 @@ void launch_cg_update_batched(const WorkList& W, hipStream_t s) {
 }
 
 template <class T>
-void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by) {
+void launch_neg_apply_dot_batched(const WorkList& W, hipStream_t s, int by, bool h16) {
   if (W.total <= 0) return;
-  residual_dot_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  if (h16)
+    residual_dot_batched<T, 1><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  else
+    residual_dot_batched<T, 0><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   MCW_CHECK_LAUNCH();
 }
 
@@ -1648,9 +1661,16 @@ void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStr
 }
 
 template <class T>
-void launch_residual_batched(const WorkList& W, hipStream_t s, int by) {
+void launch_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16) {
   if (W.total <= 0) return;
-  residual_batched<T><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  if constexpr (sizeof(T) == 4) {
+    if (h16) {
+      residual_batched<T, 1><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+      MCW_CHECK_LAUNCH();
+      return;
+    }
+  }
+  residual_batched<T, 0><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   MCW_CHECK_LAUNCH();
 }
 
@@ -1729,8 +1749,8 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_coarse_solve<T>(int, const double*, const int*, const T*, T*,            \
                                        hipStream_t);                                            \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
-  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool);                  \
-  template void launch_residual_batched<T>(const WorkList&, hipStream_t, int);                  \
+  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool, bool);            \
+  template void launch_residual_batched<T>(const WorkList&, hipStream_t, int, bool);            \
   template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
   template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \
   template void launch_coarse_batched<T>(const WorkList&, int, hipStream_t);                    \
@@ -1741,7 +1761,7 @@ MCW_INST(double)
 template void launch_dot2_batched<float>(const WorkList&, hipStream_t);
 template void launch_cg_direction_batched<float>(const WorkList&, hipStream_t);
 template void launch_cg_update_batched<float>(const WorkList&, hipStream_t);
-template void launch_neg_apply_dot_batched<float>(const WorkList&, hipStream_t, int);
+template void launch_neg_apply_dot_batched<float>(const WorkList&, hipStream_t, int, bool);
 #undef MCW_INST
 
 }  // namespace mcw

@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -732,6 +733,7 @@ void autotune_levels(mcw_handle& h) {
       if ((which == 0 && have_gs) || (which == 1 && have_res)) continue;
       float best = 1e30f;
       int best_by = which == 0 ? 0 : 4;
+      std::string times;
       for (int by : which == 0 ? cand_gs : cand_res) {
         auto run = [&] {
           if (which == 0)
@@ -748,6 +750,9 @@ void autotune_levels(mcw_handle& h) {
         MCW_HIP(hipEventSynchronize(h.ev[7]));
         float ms = 0.f;
         MCW_HIP(hipEventElapsedTime(&ms, h.ev[6], h.ev[7]));
+        char buf[48];
+        std::snprintf(buf, sizeof buf, " %d:%.3f", by, ms / 3);
+        times += buf;
         if (ms < best) {
           best = ms;
           best_by = by;
@@ -760,8 +765,8 @@ void autotune_levels(mcw_handle& h) {
         L.by_res = best_by;
         cache.put(arch + "|res|" + dims, best_by);
       }
-      logf(h, "autotune %s %s: %d rows per block (0: fused rows)", which == 0 ? "gs" : "res", dims.c_str(),
-           best_by);
+      logf(h, "autotune %s %s: %d rows per block (0: fused rows); ms per %s:%s",
+           which == 0 ? "gs" : "res", dims.c_str(), best_by, which == 0 ? "sweep" : "launch", times.c_str());
     }
   }
   cache.save();
@@ -1152,8 +1157,8 @@ class Batch {
         fj.push_back(vec_job(C.x.p, nullptr, C.d.N(), nullptr));
         fm.push_back(i);
       }
-      for (int c = 0; c < 4; ++c) gs_[d][c] = add(gsj[c], gsm[c]);
-      res_[d] = add(rj, rm);
+      for (int c = 0; c < 4; ++c) gs_[d][c] = add_split(gsj[c], gsm[c]);
+      res_[d] = add_split(rj, rm);
       restr_[d] = add(rsj, rsm);
       prol_[d] = add(pj, pm);
       fillx_[d] = add(fj, fm);
@@ -1262,7 +1267,7 @@ class Batch {
     }
     cg_slot_ = alloc_host((size_t)m_ * 4 * sizeof(double));
     cgvec_ = add(cg_jobs_, all);
-    cgres_ = add(cr, all);
+    cgres_ = add_split(cr, all);
     cgfill_ = add(fe, all);
     cgtab_off_ = add_raw(cg_jobs_.data(), cg_jobs_.size() * sizeof(CgJob));
   }
@@ -1464,6 +1469,25 @@ class Batch {
     return W;
   }
 
+  // The work lists of one phase by stencil format (0: T values, 1: FP16), so
+  // that each launch runs the kernel instance of its format.
+  struct ByFormat {
+    WorkList w[2]{};
+    int njobs() const { return w[0].njobs + w[1].njobs; }
+  };
+  ByFormat add_split(const std::vector<ColJob>& jobs, const std::vector<int>& members) {
+    std::vector<ColJob> js[2];
+    std::vector<int> ms[2];
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      const int f = jobs[k].h16 ? 1 : 0;
+      js[f].push_back(jobs[k]);
+      ms[f].push_back(members[k]);
+    }
+    ByFormat B;
+    for (int f = 0; f < 2; ++f) B.w[f] = add(js[f], ms[f]);
+    return B;
+  }
+
   static int nblocks_of(const ColJob& J) { return J.nblocks; }
   static int nblocks_of(const XferJob& X) { return X.nblocks; }
   static int nblocks_of(const CoarseJob& C) { return C.nblocks; }
@@ -1517,10 +1541,11 @@ class Batch {
   void vcycle_levels(int d) {
     const int nu_pre = hs_[0]->opt.nu_pre, nu_post = hs_[0]->opt.nu_post;
     launch_coarse_batched<float>(fix(coarse_[d]), std::max(max_coarse_, 1), s_);
-    if (res_[d].njobs == 0) return;
+    if (res_[d].njobs() == 0) return;
     for (int s = 0; s < nu_pre; ++s)
-      for (int c = 0; c < 4; ++c) launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d]);
-    launch_residual_batched<float>(fix(res_[d]), s_, by_res_[d]);
+      for (int c = 0; c < 4; ++c)
+        for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(gs_[d][c].w[f]), s_, by_gs_[d], false, f == 1);
+    for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[d].w[f]), s_, by_res_[d], f == 1);
     launch_restrict_batched<float>(fix(restr_[d]), s_);
     launch_fill_batched<float>(fix(fillx_[d]), s_);
     if (d + 1 < depth_) vcycle_levels(d + 1);
@@ -1529,7 +1554,7 @@ class Batch {
     for (int s = 0; s < nu_post; ++s)
       for (int cc = 0; cc < 4; ++cc) {
         const int c = krylov_ ? 3 - cc : cc;
-        launch_gs_batched<float>(fix(gs_[d][c]), s_, by_gs_[d], krylov_);
+        for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(gs_[d][c].w[f]), s_, by_gs_[d], krylov_, f == 1);
       }
   }
 
@@ -1543,7 +1568,7 @@ class Batch {
     launch_dot2_batched<float>(fix(cgvec_), s_);
     launch_cg_coeff_batched(tab, m_, 0, act, s_);
     launch_cg_direction_batched<float>(fix(cgvec_), s_);
-    launch_neg_apply_dot_batched<float>(fix(cgres_), s_, by_res_[0]);
+    for (int f = 0; f < 2; ++f) launch_neg_apply_dot_batched<float>(fix(cgres_.w[f]), s_, by_res_[0], f == 1);
     launch_cg_coeff_batched(tab, m_, 1, act, s_);
     launch_cg_update_batched<float>(fix(cgvec_), s_);
     launch_cg_coeff_batched(tab, m_, 2, act, s_);
@@ -1636,12 +1661,14 @@ class Batch {
   hipGraphExec_t cg_graph_ = nullptr;
   double* host_cg_ = nullptr;
   std::vector<CgJob> cg_jobs_;
-  WorkList cgvec_{}, cgres_{}, cgfill_{};
+  WorkList cgvec_{}, cgfill_{};
+  ByFormat cgres_{};
   size_t cg_slot_ = 0, cgtab_off_ = 0;
   int depth_ = 0, max_coarse_ = 0;
-  std::vector<std::array<WorkList, 4>> gs_;
+  std::vector<std::array<ByFormat, 4>> gs_;
   std::vector<int> by_gs_, by_res_;
-  std::vector<WorkList> res_, restr_, fillx_, prol_, coarse_;
+  std::vector<ByFormat> res_;
+  std::vector<WorkList> restr_, fillx_, prol_, coarse_;
   WorkList zf_{}, rhs_{}, res64_{}, div_{}, rec_{}, sc_{}, f0_{}, up_{};
   std::vector<VecJob> zf_jobs_, sc_jobs_, f0_jobs_, up_jobs_;
   std::vector<TileJob> rhs_jobs_, res_jobs_, div_jobs_;

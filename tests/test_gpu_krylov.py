@@ -138,7 +138,7 @@ def test_graph_replay_is_bitwise_equal_to_direct_launches():
     assert torch.equal(out[0][0], out[1][0])
 
 
-def test_krylov_needs_a_symmetric_cycle_and_batches_fall_back():
+def test_krylov_needs_a_symmetric_cycle_and_batched_cg_equals_single_solves():
     mcwind = _mcw()
     with pytest.raises(mcwind.MCWError, match="nu_pre == nu_post"):
         _grid("box", krylov=True, nu_pre=2, nu_post=1)
