@@ -161,3 +161,23 @@ def test_3000x3000x15_warm_solve_with_fp16_stencils():
     diff = float((lams[0] - lams[1]).abs().max() / lams[0].abs().max())
     print(f"[case] lambda fp16 vs fp32 stencils: {diff:.2e}", flush=True)
     assert diff < 1e-5
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("scale", [1e-3, 1e3])
+def test_coordinate_scaling_with_either_stencil_format(scale, fp16):
+    """Coordinates times s: K scales by s, f by s^2, so lambda by s and u is
+    unchanged; the per-level power-of-two scale keeps FP16 stencils (and the
+    scaled residual keeps FP32 V-cycles) indifferent to the magnitudes."""
+    mcwind = _mcw()
+    p = gc.problem("ragged")
+    lam_ref, u_ref, _ = gc.solution("ragged")
+    print(f"[case] scaled coordinates s={scale} fp16={fp16}", flush=True)
+    dev = torch.device("cuda")
+    X, Y, Z = (torch.from_numpy(A * scale).to(dev) for A in (p.X, p.Y, p.Z))
+    u0 = torch.from_numpy(p.u0).to(dev)
+    g = mcwind.Grid(X, Y, Z, p.a, gamma=p.gamma, rtol=1e-12, stencil_fp16=fp16)
+    lam, u, info = g.solve(u0)
+    assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-12
+    assert gc.rel_err(lam.cpu().numpy() / scale, lam_ref) < 1e-8
+    assert gc.rel_err(u.cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8
