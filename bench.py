@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-coupling", action="store_true",
                     help="skip timing the steps around the solve")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoint")
+    ap.add_argument("--no-line", action="store_true",
+                    help="skip the solves with the vertical line smoother")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the solves with FP16 stencils (option stencil_fp16)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules", "configs"],
@@ -508,70 +510,51 @@ def main():
                 f"surface wind {ms_s:.3f} ms")
         del g
         torch.cuda.empty_cache()
-        krylov = None
-        if not args.no_krylov:
-            # the same solve by CG preconditioned with one symmetric V-cycle per step
+        def variant(label, diff_key, **kw):
+            """The same warm-started solve on a handle with other options: set-up,
+            one warm-up solve (graph capture), then timed solves from lam_prev."""
             t0 = time.perf_counter()
-            gk = mcwind.Grid(X, Y, Z, p.a, precision="fp32_refine", rtol=1e-8, krylov=True)
-            sk = time.perf_counter() - t0
-            lamk = torch.empty_like(lam_prev)
-            lamk.copy_(lam_prev)
-            gk.solve(u0p, lam=lamk, want_u=False)  # warm-up (captures the CG step graph)
+            gv = mcwind.Grid(X, Y, Z, p.a, precision="fp32_refine", rtol=1e-8, **kw)
+            sv = time.perf_counter() - t0
+            lamv = torch.empty_like(lam_prev)
+            lamv.copy_(lam_prev)
+            gv.solve(u0p, lam=lamv, want_u=False)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             reps = max(1, min(args.steps, 3))
             e0.record(stream)
             for _ in range(reps):
-                lamk.copy_(lam_prev)
-                _, _, ik = gk.solve(u0p, lam=lamk)
+                lamv.copy_(lam_prev)
+                _, _, iv = gv.solve(u0p, lam=lamv)
             e1.record(stream)
             torch.cuda.synchronize()
-            msk = e0.elapsed_time(e1) / reps
-            diff = float((lamk - lam).abs().max() / lam.abs().max())
-            krylov = {"value": round(N / msk / 1e3, 2), "ms_per_step": round(msk, 3),
-                      "cycles": ik["cycles"], "refinements": ik["outer_steps"],
-                      "rel_residual": ik["rel_residual"], "rel_divergence": ik["rel_divergence"],
-                      "rho": ik["rho"], "setup_s": round(sk, 2),
-                      "lambda_rel_diff_vs_multigrid": diff}
-            log(f"mg-pcg: {msk:.1f} ms/step, {ik['cycles']} cycles, {ik['outer_steps']} refinements, "
-                f"rel res {ik['rel_residual']:.2e}, lambda diff {diff:.2e}")
-            del gk
+            msv = e0.elapsed_time(e1) / reps
+            diff = float((lamv - lam).abs().max() / lam.abs().max())
+            out = {"value": round(N / msv / 1e3, 2), "ms_per_step": round(msv, 3),
+                   "cycles": iv["cycles"], "refinements": iv["outer_steps"],
+                   "rel_residual": iv["rel_residual"], "rel_divergence": iv["rel_divergence"],
+                   "rho": iv["rho"], "setup_s": round(sv, 2), diff_key: diff}
+            log(f"{label}: {msv:.1f} ms/step, {iv['cycles']} cycles, {iv['outer_steps']} refinements, "
+                f"rel res {iv['rel_residual']:.2e}, lambda diff {diff:.2e}")
+            del gv
             torch.cuda.empty_cache()
+            return out
+
+        # CG preconditioned with one symmetric V-cycle per step
+        krylov = None if args.no_krylov else variant("mg-pcg", "lambda_rel_diff_vs_multigrid",
+                                                     krylov=True)
+        # the V-cycle's stencils kept in FP16 (arithmetic still FP32, refinement FP64)
         half = None
         if not args.no_fp16:
-            # the same solve with the V-cycle's stencils kept in FP16 (arithmetic
-            # still FP32, refinement FP64): the multigrid iteration, then CG
-            half = {}
-            for kry in (False, True):
-                t0 = time.perf_counter()
-                gh = mcwind.Grid(X, Y, Z, p.a, precision="fp32_refine", rtol=1e-8, krylov=kry,
-                                 stencil_fp16=True)
-                sh = time.perf_counter() - t0
-                lamh = torch.empty_like(lam_prev)
-                lamh.copy_(lam_prev)
-                gh.solve(u0p, lam=lamh, want_u=False)  # warm-up (graph capture)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                reps = max(1, min(args.steps, 3))
-                e0.record(stream)
-                for _ in range(reps):
-                    lamh.copy_(lam_prev)
-                    _, _, ih = gh.solve(u0p, lam=lamh)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                msh = e0.elapsed_time(e1) / reps
-                diff = float((lamh - lam).abs().max() / lam.abs().max())
-                key = "mg_pcg" if kry else "multigrid"
-                half[key] = {"value": round(N / msh / 1e3, 2), "ms_per_step": round(msh, 3),
-                             "cycles": ih["cycles"], "refinements": ih["outer_steps"],
-                             "rel_residual": ih["rel_residual"],
-                             "rel_divergence": ih["rel_divergence"], "setup_s": round(sh, 2),
-                             "lambda_rel_diff_vs_fp32_stencils": diff}
-                log(f"fp16 stencils, {key}: {msh:.1f} ms/step, {ih['cycles']} cycles, "
-                    f"{ih['outer_steps']} refinements, rel res {ih['rel_residual']:.2e}, "
-                    f"lambda diff {diff:.2e}")
-                del gh
-                torch.cuda.empty_cache()
+            half = {key: variant(f"fp16 stencils, {key}", "lambda_rel_diff_vs_fp32_stencils",
+                                 krylov=kry, stencil_fp16=True)
+                    for key, kry in (("multigrid", False), ("mg_pcg", True))}
+        # vertical line Gauss-Seidel in place of the pointwise smoother
+        line = None
+        if not args.no_line:
+            line = {key: variant(f"line smoother, {key}", "lambda_rel_diff_vs_point_smoother",
+                                 krylov=kry, smoother="line")
+                    for key, kry in (("multigrid", False), ("mg_pcg", True))}
         fp64 = None
         if not args.no_fp64:
             t0 = time.perf_counter()
@@ -634,6 +617,7 @@ def main():
         "kernels": kernels,
         "mg_pcg": krylov,
         "fp16_stencils": half,
+        "line_smoother": line,
         "adjoint": adjoint,
         "coupling": coupling,
         "fp64_plain": fp64,
