@@ -224,12 +224,17 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
 // column's free nodes are solved together with the neighbour columns (and the
 // column's fixed end nodes) held at their current values.  The column block is
 // tridiagonal in the couplings o = 4 (below), 13 (self), 22 (above); forward
-// elimination from the bottom leaves the modified upper coefficients in J.r
-// and the modified right-hand sides in x, back substitution from the top
-// finishes x.  The solve is exact in the column, so a reverse sweep differs
-// from a forward one only in the order of the colours.
-template <class T, int SF = 0>
-__device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
+// elimination from the bottom leaves the modified upper coefficients and the
+// modified right-hand sides, back substitution from the top finishes x.  The
+// solve is exact in the column, so a reverse sweep differs from a forward one
+// only in the order of the colours.
+// With LDS the thread keeps both sequences in its own LDS slots (ls, stride
+// ls_stride; the c of free plane t at ls[t * stride], the right-hand side at
+// ls[(np + t) * stride]) and writes x once; otherwise they go to J.r and x.
+// The arithmetic is the same either way.
+template <class T, int SF = 0, bool LDS = false>
+__device__ __forceinline__ void line_column(const ColJob& J, int i, int j, T* ls = nullptr,
+                                            int ls_stride = 0) {
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   T* __restrict__ cb = static_cast<T*>(J.r);
@@ -278,8 +283,13 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
     const T den = a[13] - sub * cprev;
     const T c = sup / den;
     const T d = (s - sub * dprev) / den;
-    cb[(size_t)k * plane + cols[4]] = c;
-    x[(size_t)k * plane + cols[4]] = d;
+    if constexpr (LDS) {
+      ls[(k - kf) * ls_stride] = c;
+      ls[(kl - kf + 1 + k - kf) * ls_stride] = d;
+    } else {
+      cb[(size_t)k * plane + cols[4]] = c;
+      x[(size_t)k * plane + cols[4]] = d;
+    }
     cprev = c;
     dprev = d;
 #pragma unroll
@@ -289,27 +299,44 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j) {
     }
   }
   T xnext = dprev;  // x at kl is its modified right-hand side
-  for (int k = kl - 1; k >= kf; --k) {
-    const size_t p = (size_t)k * plane + cols[4];
-    xnext = x[p] - cb[p] * xnext;
-    x[p] = xnext;
+  if constexpr (LDS) {
+    const int np = kl - kf + 1;
+    x[(size_t)kl * plane + cols[4]] = xnext;
+    for (int k = kl - 1; k >= kf; --k) {
+      xnext = ls[(np + k - kf) * ls_stride] - ls[(k - kf) * ls_stride] * xnext;
+      x[(size_t)k * plane + cols[4]] = xnext;
+    }
+  } else {
+    for (int k = kl - 1; k >= kf; --k) {
+      const size_t p = (size_t)k * plane + cols[4];
+      xnext = x[p] - cb[p] * xnext;
+      x[p] = xnext;
+    }
   }
 }
 
-template <class T, bool REV, bool LINE, int SF = 0>
-__device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j) {
-  if (LINE) line_column<T, SF>(J, i, j);
+template <class T, bool REV, bool LINE, int SF = 0, bool LDS = false>
+__device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j, T* ls = nullptr) {
+  if constexpr (LINE) line_column<T, SF, LDS>(J, i, j, ls, (int)blockDim.x);
   else gs_column<T, REV, SF>(J, i, j);
 }
 
 // One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
 // tiles of 64 x J.by columns per block.
-template <class T, bool REV = false, bool LINE = false, int SF = 0>
-__device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
+template <class T, bool REV = false, bool LINE = false, int SF = 0, bool LDS = false>
+__device__ __forceinline__ void gs_pass_body(const ColJob& J, int b, T* ls = nullptr) {
   const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
   const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   if (ii >= J.ncx || jj >= J.ncy) return;
-  smooth_column<T, REV, LINE, SF>(J, 2 * ii + J.ci, 2 * jj + J.cj);
+  smooth_column<T, REV, LINE, SF, LDS>(J, 2 * ii + J.ci, 2 * jj + J.cj, ls);
+}
+
+// Dynamic LDS of the line smoother: 2 values per free plane for each thread.
+extern __shared__ __align__(16) unsigned char mcw_dyn_lds[];
+template <class T, bool LDS>
+__device__ __forceinline__ T* line_slots() {
+  if constexpr (LDS) return reinterpret_cast<T*>(mcw_dyn_lds) + threadIdx.x;
+  else return nullptr;
 }
 
 // Two colour passes of the same rows in one launch: colour J0 then colour J1
@@ -319,25 +346,27 @@ __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b) {
 // and gives the same result bit for bit, with one launch instead of two.
 // Each XCD takes a contiguous range of rows, so that the blocks of rows j and
 // j + 2 running there at the same time share row j + 1 in its L2.
-// Threads per block: 1024, except the FP64 line smoother, whose Thomas sweep
-// needs more than the 128 registers a 1024-thread block leaves per lane (it
-// spilled); with 512 threads it has 256.
+// Threads per block: 1024 for the pointwise smoother, 512 for the line
+// smoother, whose column solve keeps 2 values per free plane and thread in
+// LDS (60 KB for 15 planes in FP32; the FP64 Thomas sweep also needs more
+// than the 128 registers a 1024-thread block leaves per lane).
 template <class T, bool LINE>
-constexpr int fused_threads() { return sizeof(T) == 8 && LINE ? 512 : 1024; }
+constexpr int fused_threads() { return LINE ? 512 : 1024; }
 
-template <class T, bool REV, bool LINE, int SF>
+template <class T, bool REV, bool LINE, int SF, bool LDS = false>
 __global__ __launch_bounds__((fused_threads<T, LINE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
   const int j = 2 * xcd_remap(blockIdx.x, gridDim.x) + J0.cj;
+  T* ls = line_slots<T, LDS>();
   for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
-    smooth_column<T, REV, LINE, SF>(J0, 2 * ii + J0.ci, j);
+    smooth_column<T, REV, LINE, SF, LDS>(J0, 2 * ii + J0.ci, j, ls);
   __syncthreads();
   for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
-    smooth_column<T, REV, LINE, SF>(J1, 2 * ii + J1.ci, j);
+    smooth_column<T, REV, LINE, SF, LDS>(J1, 2 * ii + J1.ci, j, ls);
 }
 
-template <class T, bool REV, bool LINE, int SF>
+template <class T, bool REV, bool LINE, int SF, bool LDS = false>
 __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
-  gs_pass_body<T, REV, LINE, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
+  gs_pass_body<T, REV, LINE, SF, LDS>(J, xcd_remap(blockIdx.x, J.nblocks), line_slots<T, LDS>());
 }
 
 template <class T, int SF>
@@ -1147,6 +1176,16 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale) {
 
 // ---------------------------------------------------------------- single launches
 
+// LDS bytes of a line-smoother launch with `threads` threads per block when
+// the column solve can keep its two sequences there (at most 64 KB), else 0
+// (the sequences then go through the level's line buffer and x).
+template <class T>
+size_t line_lds_bytes(const Dims& d, const Faces& fc, int threads) {
+  const int np = fc.k_last(d.NZ()) - fc.k_first() + 1;
+  const size_t bytes = 2 * (size_t)std::max(np, 0) * (size_t)threads * sizeof(T);
+  return np > 0 && bytes <= 65536 ? bytes : 0;
+}
+
 template <class T, bool LINE, int SF>
 void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
                     hipStream_t s, int by, bool reverse) {
@@ -1159,6 +1198,17 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
       if (J0.ncy <= 0) continue;
       const int cols = std::max(J0.ncx, J1.ncx);
       const int threads = std::min(fused_threads<T, LINE>(), std::max(64, (cols + 63) / 64 * 64));
+      if constexpr (LINE) {
+        const size_t lds = line_lds_bytes<T>(d, fc, threads);
+        if (lds) {
+          if (reverse)
+            gs_fused_kernel<T, true, LINE, SF, true><<<J0.ncy, threads, lds, s>>>(J0, J1);
+          else
+            gs_fused_kernel<T, false, LINE, SF, true><<<J0.ncy, threads, lds, s>>>(J0, J1);
+          MCW_CHECK_LAUNCH();
+          continue;
+        }
+      }
       if (reverse)
         gs_fused_kernel<T, true, LINE, SF><<<J0.ncy, threads, 0, s>>>(J0, J1);
       else
@@ -1167,10 +1217,21 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
     }
     return;
   }
+  const size_t lds = LINE ? line_lds_bytes<T>(d, fc, BX * by) : 0;
   for (int cc = 0; cc < 4; ++cc) {
     const int c = reverse ? 3 - cc : cc;
     const ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
     if (J.nblocks <= 0) continue;
+    if constexpr (LINE) {
+      if (lds) {
+        if (reverse)
+          gs_pass_kernel<T, true, LINE, SF, true><<<J.nblocks, BX * by, lds, s>>>(J);
+        else
+          gs_pass_kernel<T, false, LINE, SF, true><<<J.nblocks, BX * by, lds, s>>>(J);
+        MCW_CHECK_LAUNCH();
+        continue;
+      }
+    }
     if (reverse)
       gs_pass_kernel<T, true, LINE, SF><<<J.nblocks, BX * by, 0, s>>>(J);
     else

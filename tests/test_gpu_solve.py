@@ -247,14 +247,17 @@ def test_one_row_tiles_fit_the_partial_sum_buffer(tmp_path, monkeypatch, precisi
     assert float((lam - lam2).abs().max() / lam2.abs().max()) < 1e-8
 
 
-@pytest.mark.parametrize("dims", [(160, 120, 8), (2100, 5, 5)])
+@pytest.mark.parametrize("dims", [(160, 120, 8), (2100, 5, 5), (96, 40, 20)])
 @pytest.mark.parametrize("smoother", ["point", "line"])
 @pytest.mark.parametrize("precision", ["fp32_refine", "fp64"])
 def test_fused_colour_pass_equals_four_separate_passes(tmp_path, monkeypatch, precision, smoother, dims):
     """The fused two-colour pass (one block per row) and the four separate colour
     passes give the same sweep bit for bit, forward and reverse.  The 2100-element
     rows hold about 1050 columns of a colour, more than a block's threads (1024,
-    or 512 for the FP64 line smoother), so each thread takes several columns."""
+    or 512 for the line smoother), so each thread takes several columns.  With 20
+    free planes the FP32 line smoother's column solve fits LDS in the 256-thread
+    separate passes but not in the 512-thread fused pass, which then goes through
+    the line buffer: the two storage paths give the same bits."""
     mcwind = _mcw()
     nx, ny, nz = dims
     p = inputs.hills_problem(nx, ny, nz, 4, 5, a=(1.0, 1.0, 2.0))
