@@ -589,9 +589,9 @@ def main():
                 "traffic": counted_traffic(),
                 "copy_GB/s": round(kernels["device_copy"]["GB/s"], 1),
                 "frac_of_copy": round(achieved / kernels["device_copy"]["GB/s"], 4),
-                "kernel": ("gs_fused_kernel<float, false, false, 0> (fine-grid colour passes, two per launch)"
+                "kernel": ("gs_fused_kernel<float, false, false, 0, false> (fine-grid colour passes, two per launch)"
                            if k["launches_per_sweep"] == 2 else
-                           "gs_pass_kernel<float, false, false, 0> (fine-grid colour pass)"),
+                           "gs_pass_kernel<float, false, false, 0, false> (fine-grid colour pass)"),
                 "bytes_per_launch": k["bytes"], "ms_per_launch": round(k["ms"], 4)}
     cpu = None
     if not args.no_cpu_baseline:
