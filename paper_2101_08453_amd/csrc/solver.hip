@@ -703,23 +703,24 @@ class TuneCache {
   bool dirty_ = false;
 };
 
-// Where the fine level's stencil and vectors sit in physical memory moves its
+// Where a level's stencil and vectors sit in physical memory moves its
 // colour pass and residual by up to about 15 %: at 3000 x 3000 x 15 the same
 // buffers in different allocations took 2.70-3.22 ms per sweep and 2.89-3.45
 // ms per residual, each allocation keeping its speed, and neither the virtual
 // addresses nor fixed offsets inside one allocation predicted it.  So set-up
-// times a few placements (fresh allocations, the stencil copied over) and
-// keeps the fastest; all placements give the same results.  Rejected
-// placements are held until the probing ends, so that every trial gets new
-// memory, and probing stops early when free memory runs short.
+// times a few placements of every level with at least 2^22 nodes (fresh
+// allocations, the stencil copied over) and keeps the fastest; all placements
+// give the same results.  Rejected placements are held until the level's
+// probing ends, so that every trial gets new memory, and probing stops early
+// when free memory runs short.
 constexpr int kPlacementTrials = 4;
 
 template <class T>
-void probe_fine_placement(mcw_handle& h) {
-  if (h.levels.size() < 2) return;
-  Level& L = h.levels[0];
+void probe_placement(mcw_handle& h, size_t l) {
+  if (l + 1 >= h.levels.size()) return;  // the coarsest level has no smoother
+  Level& L = h.levels[l];
   const size_t n = L.d.N();
-  if (n < ((size_t)1 << 24)) return;
+  if (n < ((size_t)1 << 22)) return;
   DevBuf& st = L.st16.p ? L.st16 : (L.st32.p ? L.st32 : L.st64);
   const size_t vb = n * sizeof(T), need = st.bytes + 3 * vb;
   const int nu = std::max(1, h.opt.nu_pre + h.opt.nu_post);
@@ -783,7 +784,7 @@ void probe_fine_placement(mcw_handle& h) {
   }
   MCW_HIP(hipStreamSynchronize(h.stream));
   launch_fill<T>(L.x.as<T>(), n, T(0), h.stream);
-  logf(h, "fine-level placements, ms per sweep/residual: %s; kept %.3f ms per cycle", log.c_str(), best);
+  logf(h, "level %zu placements, ms per sweep/residual: %s; kept %.3f ms per cycle", l, log.c_str(), best);
 }
 
 // Time rows-per-block candidates of the colour pass and the residual on every
@@ -1044,13 +1045,12 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
   h.scalars.alloc(16 * sizeof(double));
   MCW_HIP(hipHostMalloc((void**)&h.host_scalars, 8 * sizeof(double), hipHostMallocDefault));
   if (opt.autotune) {
-    if (f32) {
-      probe_fine_placement<float>(h);
-      autotune_levels<float>(h);
-    } else {
-      probe_fine_placement<double>(h);
-      autotune_levels<double>(h);
+    for (size_t l = 0; l < h.levels.size(); ++l) {
+      if (f32) probe_placement<float>(h, l);
+      else probe_placement<double>(h, l);
     }
+    if (f32) autotune_levels<float>(h);
+    else autotune_levels<double>(h);
   }
   MCW_HIP(hipStreamSynchronize(h.stream));
   if (opt.verbose) {
