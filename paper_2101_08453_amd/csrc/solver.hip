@@ -758,10 +758,16 @@ void probe_placement(mcw_handle& h, size_t l) {
     MCW_HIP(hipMemGetInfo(&free_b, &total_b));
     if (free_b < 2 * need + ((size_t)4 << 30)) break;
     DevBuf s2, x2, f2, r2;
-    s2.alloc(st.bytes);
-    x2.alloc(vb);
-    f2.alloc(vb);
-    r2.alloc(vb);
+    try {
+      s2.alloc(st.bytes);
+      x2.alloc(vb);
+      f2.alloc(vb);
+      r2.alloc(vb);
+    } catch (const Error& e) {
+      if (e.status != MCW_OOM) throw;
+      (void)hipGetLastError();  // a failed trial only ends the probing
+      break;
+    }
     MCW_HIP(hipMemcpyAsync(s2.p, st.p, st.bytes, hipMemcpyDeviceToDevice, h.stream));
     std::swap(st, s2);
     std::swap(L.x, x2);
