@@ -555,6 +555,11 @@ def main():
             line = {key: variant(f"line smoother, {key}", "lambda_rel_diff_vs_point_smoother",
                                  krylov=kry, smoother="line")
                     for key, kry in (("multigrid", False), ("mg_pcg", True))}
+            if not args.no_fp16:
+                # the options together: CG, line smoother, FP16 stencils
+                line["mg_pcg_fp16_stencils"] = variant(
+                    "line smoother, mg_pcg, fp16 stencils", "lambda_rel_diff_vs_point_smoother",
+                    krylov=True, smoother="line", stencil_fp16=True)
         fp64 = None
         if not args.no_fp64:
             t0 = time.perf_counter()

@@ -324,3 +324,22 @@ def test_3000x3000x15_warm_solve_sampled_against_oracle():
     Xw, Yw, Zw = (A[:, 1000:1031, 2000:2031] for A in (p.X, p.Y, p.Z))
     u_ref = fem.recover(Xw, Yw, Zw, q.u0[:, :, 1000:1030, 2000:2030], p.a, lw)
     assert gc.rel_err(u_h, u_ref) < 1e-12
+
+
+def test_placement_probing_and_autotune_do_not_change_results(tmp_path, monkeypatch):
+    """Set-up with autotune on times several placements of every level of at
+    least 2^22 nodes (here the fine one) and the tile shapes; the solution is
+    the same bits as with autotune off."""
+    mcwind = _mcw()
+    monkeypatch.setenv("MCW_TUNE_CACHE", str(tmp_path / "tune.json"))
+    p = inputs.fractal_problem(600, 600, 12, 300.0, 7, a=(1.0, 1.0, 5.0))
+    assert p.n_nodes >= 1 << 22
+    out = []
+    for autotune in (True, False):
+        print(f"[case] 600x600x12 autotune={autotune}", flush=True)
+        g, u0 = mcwind.grid_from_problem(p, autotune=autotune, rtol=1e-9)
+        lam, u, info = g.solve(u0)
+        assert info["status"] == "MCW_OK"
+        out.append((lam, u))
+        g.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
