@@ -734,7 +734,7 @@ void probe_placement(mcw_handle& h, size_t l) {
     MCW_HIP(hipEventElapsedTime(&ms, h.ev[6], h.ev[7]));
     return ms / 3;
   };
-  // one V-cycle's fine-level work: nu sweeps and one residual
+  // one V-cycle's work on this level: nu sweeps and one residual
   auto cost = [&](float* sweep_ms, float* res_ms) {
     launch_fill<T>(L.f.as<T>(), n, T(0), h.stream);
     launch_fill<T>(L.x.as<T>(), n, T(0), h.stream);
