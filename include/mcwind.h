@@ -116,7 +116,13 @@ typedef struct {
   int32_t verbose;            /* print setup and convergence lines to stderr; default 0 */
   int32_t autotune;           /* time tile shapes of the colour pass and residual per level at
                                  set-up and keep the fastest (cached in the JSON file named by
-                                 MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); default 1 */
+                                 MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); before that,
+                                 on every level of at least 2^22 nodes, time up to 4 physical
+                                 placements of its stencil and vectors (fresh allocations) and
+                                 keep the fastest: set-up then holds up to 3 extra copies of
+                                 that level's stencil and vectors until the level is done, and
+                                 stops early when free memory is short.  Results do not depend
+                                 on either choice; default 1 */
   int32_t krylov;             /* 0: the multigrid iteration of Sec. 3 (default); 1: conjugate
                                  gradients preconditioned by one symmetric V-cycle (the
                                  post-smoothing sweeps run in reverse: colours 3..0, each
