@@ -117,9 +117,9 @@ typedef struct {
   int32_t autotune;           /* time tile shapes of the colour pass and residual per level at
                                  set-up and keep the fastest (cached in the JSON file named by
                                  MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); before that,
-                                 on every level of at least 2^22 nodes, time up to 4 physical
+                                 on every level of at least 2^22 nodes, time up to 6 physical
                                  placements of its stencil and vectors (fresh allocations) and
-                                 keep the fastest: set-up then holds up to 3 extra copies of
+                                 keep the fastest: set-up then holds up to 5 extra copies of
                                  that level's stencil and vectors until the level is done, and
                                  stops early when free memory is short.  Results do not depend
                                  on either choice; default 1 */

@@ -713,7 +713,7 @@ class TuneCache {
 // give the same results.  Rejected placements are held until the level's
 // probing ends, so that every trial gets new memory, and probing stops early
 // when free memory runs short.
-constexpr int kPlacementTrials = 4;
+constexpr int kPlacementTrials = 6;
 
 template <class T>
 void probe_placement(mcw_handle& h, size_t l) {
