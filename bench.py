@@ -381,7 +381,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              f"(every box here has a single MI355X)", file=sys.stderr)
+              f"(the solve runs on a single MI355X; several GPUs would split the grid "
+              f"into column blocks with halo exchange, which is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
