@@ -181,3 +181,18 @@ def test_coordinate_scaling_with_either_stencil_format(scale, fp16):
     assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-12
     assert gc.rel_err(lam.cpu().numpy() / scale, lam_ref) < 1e-8
     assert gc.rel_err(u.cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8
+
+
+@pytest.mark.parametrize("name", gc.CASES)
+def test_cg_with_line_smoother_and_fp16_stencils_matches_oracle(name):
+    """The three options together (CG preconditioned by the symmetric V-cycle,
+    vertical line smoother, FP16 stencils) reach the oracle's solution."""
+    mcwind = _mcw()
+    p = gc.problem(name)
+    lam_ref, u_ref, _ = gc.solution(name)
+    print(f"[case] cg + line + fp16 {name}", flush=True)
+    g, u0 = mcwind.grid_from_problem(p, krylov=True, smoother="line", stencil_fp16=True, rtol=1e-12)
+    lam, u, info = g.solve(u0)
+    assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-12
+    assert gc.rel_err(lam.cpu().numpy(), lam_ref) < 1e-8
+    assert gc.rel_err(u.cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8
