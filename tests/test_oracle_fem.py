@@ -156,6 +156,64 @@ def test_volumes_of_box_grid():
     assert np.allclose(v[0], 6.0) and np.allclose(v[1], 9.0)
 
 
+# ---------------------------------------------------------------- geometry check (Sec. 2)
+
+def _one_element(corners):
+    """X, Y, Z of a 1x1x1 grid from the 8 corner positions, corner a = i' + 2j' + 4k'."""
+    X, Y, Z = (np.empty((2, 2, 2)) for _ in range(3))
+    for a in range(8):
+        i, j, k = a & 1, (a >> 1) & 1, a >> 2
+        X[k, j, i], Y[k, j, i], Z[k, j, i] = corners[a]
+    return X, Y, Z
+
+
+def test_min_detJ_of_a_parallelepiped():
+    """An affine element x = x0 + M s (s in [0,1]^3) has dx/dxi = M/2 everywhere,
+    so det J = det(M)/8 at every Gauss point and at the centre; a mirrored
+    (left-handed) element has the opposite sign."""
+    rng = np.random.default_rng(7)
+    M = np.diag([30.0, 25.0, 6.0]) + rng.uniform(-3.0, 3.0, (3, 3))
+    x0 = rng.uniform(-100.0, 100.0, 3)
+    s = [np.array([a & 1, (a >> 1) & 1, a >> 2], dtype=float) for a in range(8)]
+    d = fem.min_detJ(*_one_element([x0 + M @ sa for sa in s]))
+    assert d.shape == (1,)
+    assert abs(d[0] - np.linalg.det(M) / 8.0) <= 1e-12 * abs(np.linalg.det(M))
+    Mm = M @ np.diag([-1.0, 1.0, 1.0])
+    dm = fem.min_detJ(*_one_element([x0 + Mm @ sa for sa in s]))
+    assert abs(dm[0] + np.linalg.det(M) / 8.0) <= 1e-12 * abs(np.linalg.det(M))
+
+
+@pytest.mark.parametrize("corner", range(8))
+@pytest.mark.parametrize("t", [0.3, 0.8])
+def test_min_detJ_of_a_box_with_one_corner_pushed_in(corner, t):
+    """Box h1 x h2 x h3 whose corner c (bits b_d) is moved towards the opposite
+    corner by t h_d along every axis.  With s in [0,1]^3 and
+    q_d = s_d if b_d = 1 else 1 - s_d, the map is x_d = h_d s_d - t h_d sgn_d N_c(s),
+    N_c = q_1 q_2 q_3, sgn_d = 2 b_d - 1, so dx/ds = diag(h)(I - t sgn g^T) with
+    g_m = sgn_m prod_{d != m} q_d, a rank-one update:
+        det(dx/ds) = h1 h2 h3 (1 - t (q2 q3 + q1 q3 + q1 q2)),  det J = det(dx/ds) / 8.
+    q_d is (1 +- 1/sqrt 3)/2 at the Gauss points and 1/2 at the centre, so the
+    minimum over the nine points is at the single Gauss point nearest to c,
+    (h1 h2 h3 / 8)(1 - 3 t q+^2) with q+ = (1 + 1/sqrt 3)/2, and the centre
+    gives (h1 h2 h3 / 8)(1 - 3t/4).  At t = 0.8 the element is inverted at
+    that Gauss point only (-0.49) while the centre stays positive (+0.4): a
+    check at the centre alone, or one that skips a Gauss point, misses it."""
+    h = np.array([30.0, 20.0, 5.0])
+    b = np.array([corner & 1, (corner >> 1) & 1, corner >> 2], dtype=float)
+    sgn = 2.0 * b - 1.0
+    corners = []
+    for a in range(8):
+        s = np.array([a & 1, (a >> 1) & 1, a >> 2], dtype=float)
+        x = h * s - (t * h * sgn if a == corner else 0.0)
+        corners.append(x)
+    d = fem.min_detJ(*_one_element(corners))[0]
+    qp = (1.0 + 1.0 / math.sqrt(3.0)) / 2.0
+    vol = h.prod()
+    assert abs(d - vol / 8.0 * (1.0 - 3.0 * t * qp * qp)) <= 1e-12 * vol
+    assert (d <= 0.0) == (t == 0.8)
+    assert vol / 8.0 * (1.0 - 0.75 * t) > 0.0  # the centre alone would accept every case
+
+
 # ---------------------------------------------------------------- special case (Q3)
 
 def test_flat_terrain_horizontal_wind_gives_zero_multiplier():

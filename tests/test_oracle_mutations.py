@@ -191,7 +191,31 @@ def _cg_beta_inverted(mp):
     mp.setattr(mg.Multigrid, "pcg", bad)
 
 
+def _geometry_at_centre_only(mp):
+    def bad(X, Y, Z):
+        nx, ny, nz = fem.dims_of(X)
+        xe = fem.element_coords(X, Y, Z, fem.element_node_ids(nx, ny, nz))
+        return np.linalg.det(fem.jacobian(xe, fem.CENTRE))
+    mp.setattr(fem, "min_detJ", bad)
+
+
+def _geometry_without_last_gauss_point(mp):
+    def bad(X, Y, Z):
+        nx, ny, nz = fem.dims_of(X)
+        xe = fem.element_coords(X, Y, Z, fem.element_node_ids(nx, ny, nz))
+        pts = list(fem.GAUSS_POINTS[:-1]) + [fem.CENTRE]
+        return np.min(np.stack([np.linalg.det(fem.jacobian(xe, xi)) for xi in pts], 1), 1)
+    mp.setattr(fem, "min_detJ", bad)
+
+
+def _pushed_corners():
+    return [(t_fem.test_min_detJ_of_a_box_with_one_corner_pushed_in, (c, t))
+            for c in range(8) for t in (0.3, 0.8)]
+
+
 MUTATIONS = {
+    "geometry checked at the centre only": (_geometry_at_centre_only, _pushed_corners),
+    "geometry check skips a Gauss point": (_geometry_without_last_gauss_point, _pushed_corners),
     "Gauss points at +-1/2": (_gauss_at_half, lambda: [
         (t_fem.test_box_element_is_tensor_product, ((30.0, 25.0, 5.0), (1.0, 1.0, 1.0))),
         (t_fem.test_cube_interior_stencil, ())]),
