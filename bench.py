@@ -142,9 +142,59 @@ def kernel_table(g, stream, n_free):
     return out
 
 
-def cpu_baseline(p, du, n_sample=240):
+# node windows (i0, i1, j0, j1) where the oracle recomputes f - K lambda of the
+# GPU's lambda: a corner, the interior and an edge of the 3000 x 3000 grid
+CHECK_WINDOWS = [(0, 20, 0, 20), (1490, 1512, 1480, 1500), (2985, 3001, 10, 30)]
+
+
+def gpu_windows(g, lam, u0p, f_norm, dims):
+    """Host copies, for each check window, of lambda with a one-node margin and of
+    the GPU's own residual f - K lambda there (free rows; the library's kernels)."""
+    import torch
+    nx, ny, _ = dims
+    r = g.rhs(u0p) - g.apply_K(lam)
+    out = []
+    for (i0, i1, j0, j1) in CHECK_WINDOWS:
+        i1, j1 = min(i1, nx + 1), min(j1, ny + 1)
+        if i0 >= i1 or j0 >= j1:
+            continue
+        a0, a1, b0, b1 = max(i0 - 1, 0), min(i1 + 1, nx + 1), max(j0 - 1, 0), min(j1 + 1, ny + 1)
+        out.append({"win": (i0, i1, j0, j1), "margin": (a0, a1, b0, b1),
+                    "lam": lam[:, b0:b1, a0:a1].cpu().numpy(),
+                    "r": r[:, j0:j1, i0:i1].cpu().numpy()})
+    del r
+    torch.cuda.empty_cache()
+    return {"f_norm": f_norm, "windows": out}
+
+
+def oracle_window_check(p, du, gw):
+    """The oracle's FP64 f - K lambda of the GPU's lambda on the check windows
+    (the rows of K there involve only elements inside the window plus margin):
+    its largest entry and its largest difference from the GPU's own residual,
+    both relative to ||f||."""
+    from oracle import fem
+    worst_r = worst_d = 0.0
+    for w in gw["windows"]:
+        (i0, i1, j0, j1), (a0, a1, b0, b1) = w["win"], w["margin"]
+        X, Y, Z = (np.ascontiguousarray(A[:, b0:b1, a0:a1]) for A in (p.X, p.Y, p.Z))
+        u0 = np.ascontiguousarray(p.u0[:, :, b0:b1 - 1, a0:a1 - 1] + du[:, :, b0:b1 - 1, a0:a1 - 1])
+        K = fem.assemble_stiffness(X, Y, Z, p.a)
+        f = fem.assemble_rhs(X, Y, Z, u0)
+        r = (f - K @ w["lam"].ravel()).reshape(w["lam"].shape)[:, j0 - b0:j1 - b0, i0 - a0:i1 - a0]
+        m = fem.free_mask(*p.dims, p.gamma)[:, j0:j1, i0:i1]
+        r = np.where(m, r, 0.0)
+        worst_r = max(worst_r, float(np.abs(r).max()))
+        worst_d = max(worst_d, float(np.abs(r - np.where(m, w["r"], 0.0)).max()))
+    return {"windows": [w["win"] for w in gw["windows"]],
+            "max_abs_residual_rel_f": worst_r / gw["f_norm"],
+            "max_abs_diff_vs_gpu_residual_rel_f": worst_d / gw["f_norm"]}
+
+
+def cpu_baseline(p, du, gw=None, n_sample=240):
     """The FP64 oracle (as it stands) on a bounded window of the same workload:
-    the first n_sample x n_sample element columns of the perturbed wind problem."""
+    the first n_sample x n_sample element columns of the perturbed wind problem.
+    With gw (gpu_windows), the oracle also recomputes the residual of the GPU's
+    lambda on the check windows."""
     from threadpoolctl import threadpool_limits
 
     from oracle import solve as osolve
@@ -158,12 +208,17 @@ def cpu_baseline(p, du, n_sample=240):
         t0 = time.perf_counter()
         lam, u, info = osolve.solve(w, method="cg", rtol=1e-8)
         t = time.perf_counter() - t0
-    return {
+    out = {
         "value": w.n_nodes / t / 1e6, "unit": "Mnodes/s", "cores": 1, "kind": "oracle",
+        "host_cpus": os.cpu_count(),
         "sample": (f"{m}x{m}x{p.dims[2]} corner window of the same grid and perturbed wind, "
                    f"cold Jacobi-PCG to rel. residual 1e-8 incl. assembly and recovery: "
-                   f"{t:.1f} s, {info['iterations']} CG iterations, 1 thread"),
+                   f"{t:.1f} s, {info['iterations']} CG iterations, 1 thread of "
+                   f"{os.cpu_count()} host CPUs"),
     }
+    if gw is not None:
+        out["gpu_lambda_vs_oracle"] = oracle_window_check(p, du, gw)
+    return out
 
 
 def bench_c4(args):
@@ -285,24 +340,29 @@ def bench_c4(args):
 
 
 def bench_configs(args):
-    """The configurations the oracle finishes on the host in a minute or two
-    (32x32x8 Gaussian hill, 256x256x16 with 40 hills): GPU solves in both
-    precisions and the oracle's cold Jacobi-PCG solve, each to relative
-    residual 1e-8 from lambda = 0, with the error of the GPU's lambda against
-    the oracle's."""
+    """The smaller configurations: 32x32x8 Gaussian hill, 256x256x16 with 40
+    hills, and 512x512x15 fractal terrain (500 m relief).  GPU solves in both
+    precisions to relative residual 1e-8 from lambda = 0, with the V-cycle rate
+    (also with the coarsened spacing in the layer test of the coarsening rule,
+    as printed); on the first two, the oracle's cold Jacobi-PCG solve (host
+    CPU) and the error of the GPU's lambda against it."""
     import torch
     from threadpoolctl import threadpool_limits
 
     from oracle import solve as osolve
     from paper_2101_08453_amd import inputs, mcwind
     rows = []
-    for name, make in (("32x32x8 gaussian hill", inputs.c1), ("256x256x16 40 hills", inputs.c2)):
+    for name, make, oracle in (("32x32x8 gaussian hill", inputs.c1, True),
+                               ("256x256x16 40 hills", inputs.c2, True),
+                               ("512x512x15 fractal 500 m", inputs.c5, False)):
         p = make()
         row = {"config": name, "nodes": p.n_nodes}
-        for prec in ("fp32_refine", "fp64"):
-            g, u0 = mcwind.grid_from_problem(p, precision=prec, rtol=1e-8)
+        for key, kw in (("fp32_refine", dict(precision="fp32_refine")),
+                        ("fp64", dict(precision="fp64")),
+                        ("fp64_coarsened_spacing", dict(precision="fp64", merge_spacing="coarsened"))):
+            g, u0 = mcwind.grid_from_problem(p, rtol=1e-8, **kw)
             lam = g._node()
-            g.solve(u0, lam=lam)  # warm-up (graph capture, caches)
+            g.solve(u0, lam=lam)  # warm-up (graph capture, caches, the measured rate)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             reps = 5
@@ -313,29 +373,35 @@ def bench_configs(args):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
-            row[prec] = {"ms": round(ms, 3), "Mnodes/s": round(p.n_nodes / ms / 1e3, 2),
-                         "cycles": info["cycles"], "rel_residual": info["rel_residual"]}
-            row[prec + "_lambda"] = lam.cpu().numpy()
+            row[key] = {"ms": round(ms, 3), "Mnodes/s": round(p.n_nodes / ms / 1e3, 2),
+                        "cycles": info["cycles"], "rho": round(info["rho"], 3),
+                        "rel_residual": info["rel_residual"], "levels": info["levels"]}
+            row[key + "_lambda"] = lam.cpu().numpy()
             g.close()
-        log(f"{name}: GPU done, oracle running")
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            lam_o, _, oinfo = osolve.solve(p, method="cg", rtol=1e-8)
-            t = time.perf_counter() - t0
-        row["oracle"] = {"s": round(t, 2), "Mnodes/s": round(p.n_nodes / t / 1e6, 4), "cores": 1,
-                         "iterations": oinfo["iterations"], "method": oinfo["method"]}
-        for prec in ("fp32_refine", "fp64"):
-            lg = row.pop(prec + "_lambda")
-            row[prec]["lambda_rel_diff_vs_oracle"] = float(np.abs(lg - lam_o).max() / np.abs(lam_o).max())
+            log(f"{name} {key}: {ms:.2f} ms, {info['cycles']} cycles, rho {info['rho']:.3f}")
+        if oracle:
+            log(f"{name}: GPU done, oracle running")
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                lam_o, _, oinfo = osolve.solve(p, method="cg", rtol=1e-8)
+                t = time.perf_counter() - t0
+            row["oracle"] = {"s": round(t, 2), "Mnodes/s": round(p.n_nodes / t / 1e6, 4),
+                             "cores": 1, "host_cpus": os.cpu_count(),
+                             "iterations": oinfo["iterations"], "method": oinfo["method"]}
+        for key in ("fp32_refine", "fp64", "fp64_coarsened_spacing"):
+            lg = row.pop(key + "_lambda")
+            if oracle:
+                row[key]["lambda_rel_diff_vs_oracle"] = float(np.abs(lg - lam_o).max() / np.abs(lam_o).max())
         log(row)
         rows.append(row)
-    print(json.dumps({"workload": "oracle-sized configurations", "host_cpus": os.cpu_count(),
-                      "rows": rows}), flush=True)
+    print(json.dumps({"workload": "configurations 32x32x8, 256x256x16, 512x512x15",
+                      "host_cpus": os.cpu_count(), "rows": rows}), flush=True)
 
 
 def bench_rules(args):
     """Base method (full 2x2x2 coarsening) against adaptive semicoarsening (the
-    operator-consistent and the printed ratio) on 512x512x15 fractal terrain
+    operator-consistent and the printed ratio; the layer test with the level's
+    own or the coarsened horizontal spacing) on 512x512x15 fractal terrain
     with the slopes of the 3000x3000 grid, for a3 in {1, 2, 5, 10} and layer
     stretching 1.0 / 1.2: V-cycles and rate to 1e-8 (plain FP64, cold start),
     by the multigrid iteration and by multigrid-preconditioned CG, with the
@@ -353,12 +419,14 @@ def bench_rules(args):
             X, Y, Z = inputs.terrain_grid(zs, zeta, 30.0, 30.0)
             u0 = inputs._log_wind(n, n, nz, zeta, 8.0, 0.3)
             p = inputs.Problem("rules", X, Y, Z, u0, np.array([1.0, 1.0, a3]))
-            for rule in ("operator", "literal", "full"):
+            for rule in ("operator", "operator:coarsened", "literal", "full"):
                 for smoother in ("point", "line"):
-                    if rule == "literal" and smoother == "line":
+                    if rule in ("literal", "operator:coarsened") and smoother == "line":
                         continue
                     for krylov in (False, True):
-                        g, u0t = mcwind.grid_from_problem(p, precision="fp64", coarsen_rule=rule,
+                        r, _, spacing = rule.partition(":")
+                        g, u0t = mcwind.grid_from_problem(p, precision="fp64", coarsen_rule=r,
+                                                          merge_spacing=spacing or "level",
                                                           max_cycles=400, krylov=krylov,
                                                           smoother=smoother)
                         g.solve(u0t, check=False, want_u=False)  # warm-up (graph capture)
@@ -490,6 +558,10 @@ def main():
             log(f"adjoint: {ms_a:.1f} ms, {ia['cycles']} cycles (cold transpose solve), "
                 f"dL/da {d_a[0]:.3e} {d_a[1]:.3e} {d_a[2]:.3e}")
             del lam_a, u_a, g_u, d_u0, mask
+        gw = None
+        if not args.no_cpu_baseline:
+            # the timed solve's lambda, for the oracle's residual check on windows
+            gw = gpu_windows(g, lam, u0p, info["f_norm"], p.dims)
         coupling = None
         if not args.no_coupling:
             # the steps around the solve: a coarse wind every 600 m (40 levels) to the
@@ -533,6 +605,7 @@ def main():
             diff = float((lamv - lam).abs().max() / lam.abs().max())
             out = {"value": round(N / msv / 1e3, 2), "ms_per_step": round(msv, 3),
                    "cycles": iv["cycles"], "refinements": iv["outer_steps"],
+                   "levels": iv["levels"],
                    "rel_residual": iv["rel_residual"], "rel_divergence": iv["rel_divergence"],
                    "rho": iv["rho"], "setup_s": round(sv, 2), diff_key: diff}
             log(f"{label}: {msv:.1f} ms/step, {iv['cycles']} cycles, {iv['outer_steps']} refinements, "
@@ -541,6 +614,10 @@ def main():
             torch.cuda.empty_cache()
             return out
 
+        # the layer test of the coarsening rule with the coarsened horizontal
+        # spacing, as printed, instead of the level's own
+        printed = variant("coarsened spacing in the layer test", "lambda_rel_diff_vs_multigrid",
+                          merge_spacing="coarsened")
         # CG preconditioned with one symmetric V-cycle per step
         krylov = None if args.no_krylov else variant("mg-pcg", "lambda_rel_diff_vs_multigrid",
                                                      krylov=True)
@@ -602,7 +679,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(p, du)
+        cpu = cpu_baseline(p, du, gw)
         log(f"cpu baseline: {cpu['value']:.4f} Mnodes/s ({time.perf_counter() - t0:.1f} s)")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mnodes/s", "n_gpus": 1,
@@ -621,6 +698,7 @@ def main():
                   "history": [float(f"{v:.3e}") for v in info["history"]]},
         "roofline": roof,
         "kernels": kernels,
+        "coarsened_spacing_rule": printed,
         "mg_pcg": krylov,
         "fp16_stencils": half,
         "line_smoother": line,

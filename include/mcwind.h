@@ -85,6 +85,18 @@ typedef enum {
 } mcw_coarsen_rule;
 
 typedef enum {
+  /* the layer test of the semicoarsening rule (Sec. 3) compares each layer with
+     the horizontal spacing of the level being coarsened, so that both thresholds
+     bound the coupling anisotropy of the grid the smoother runs on by 9 */
+  MCW_MERGE_LEVEL_SPACING = 0,
+  /* it compares with the spacing after the horizontal step (twice the level's
+     when the level coarsens horizontally), as printed in Sec. 3: merged pairs
+     can then reach coupling anisotropy 36, and the cycle converges more slowly
+     on stretched layers */
+  MCW_MERGE_COARSENED_SPACING = 1
+} mcw_merge_spacing;
+
+typedef enum {
   /* Sec. 3: pointwise Gauss-Seidel, each column from the bottom up, colours
      (0,0),(1,0),(0,1),(1,1) */
   MCW_SMOOTH_POINT = 0,
@@ -109,14 +121,16 @@ typedef struct {
   double rtol;                /* stop when ||f - K lambda||_2 <= rtol ||f||_2 (free nodes); default 1e-8 */
   int32_t max_cycles;         /* V-cycles per solve before MCW_NOT_CONVERGED; default 200 */
   int32_t nu_pre, nu_post;    /* Gauss-Seidel sweeps before / after the coarse correction; default 2, 2 */
-  int32_t inner_cycles;       /* FP32 V-cycles per refinement step; 0 = chosen from the measured rate */
+  int32_t inner_cycles;       /* FP32 V-cycles per refinement step; 0 = chosen from the V-cycle
+                                 rate (measured at set-up from a fixed pseudo-random right-hand
+                                 side, then from the solve's own refinement steps) */
   int32_t coarsen_rule;       /* mcw_coarsen_rule; default MCW_COARSEN_OPERATOR */
   int32_t coarse_direct_max;  /* largest coarsest-level unknown count (direct solve); default 1024, max 4096 */
   int32_t use_graph;          /* capture the FP32 V-cycle in a hipGraph and replay it; default 1 */
   int32_t verbose;            /* print setup and convergence lines to stderr; default 0 */
   int32_t autotune;           /* time tile shapes of the colour pass and residual per level at
-                                 set-up and keep the fastest (cached in the JSON file named by
-                                 MCW_TUNE_CACHE, else ~/.cache/mcwind/tune.json); before that,
+                                 set-up and keep the fastest (cached in the file tune_cache
+                                 names); before that,
                                  on every level of at least 2^22 nodes, time up to 6 physical
                                  placements of its stencil and vectors (fresh allocations) and
                                  keep the fastest: set-up then holds up to 5 extra copies of
@@ -136,6 +150,10 @@ typedef struct {
                                  refinement in FP64, so the solution meets rtol as before.  One
                                  refinement step then reduces the residual by at most about 1e-3
                                  (3e-5 with FP32 stencils).  Not part of the paper's method. */
+  int32_t merge_spacing;      /* mcw_merge_spacing; default MCW_MERGE_LEVEL_SPACING */
+  const char* tune_cache;     /* host string, the autotuner's JSON cache file; NULL = the file
+                                 named by the environment variable MCW_TUNE_CACHE, else
+                                 ~/.cache/mcwind/tune.json; "" = no cache.  Copied by mcw_create. */
 } mcw_options;
 
 #define MCW_MAX_LEVELS 24
@@ -165,7 +183,8 @@ typedef struct mcw_handle mcw_handle;
 /* Fill o with the defaults listed above. */
 void mcw_default_options(mcw_options* o);
 
-/* Set up a grid (Sec. 2 discretisation, Sec. 3 hierarchy): validates the
+/* Set up a grid (Sec. 2, discretisation of eq. (5); Sec. 3, coarsening rule
+ * and eq. (7) for the coarse operators): validates the
  * arguments, checks det J > 0 at every Gauss point and element centre,
  * assembles the 27-point fine stiffness stencil from 2x2x2 Gauss quadrature,
  * chooses the coarse grids by the coarsening rule, forms the Galerkin
@@ -184,7 +203,10 @@ void mcw_destroy(mcw_handle* h);
  * (rtol in (0,1), max_cycles >= 1); the hierarchy and operators are kept. */
 mcw_status mcw_set_tolerance(mcw_handle* h, double rtol, int32_t max_cycles);
 
-/* Solve for the multiplier and recover the wind.
+/* Solve for the multiplier and recover the wind (Sec. 2): lambda solves the
+ * discrete eq. (5) with lambda = 0 on the boundary outside Gamma (eq. (4)),
+ * by the multigrid iteration of Sec. 3 (eqs. (6)-(7)), and u follows from
+ * eq. (3) at the element centres.
  * u0:     device, (3, nz, ny, nx) FP64 initial wind at element centres.
  * lambda: device, N FP64; on entry the starting guess (warm start from the
  *         previous time step; zeros = cold start; entries at fixed nodes are
@@ -195,12 +217,15 @@ mcw_status mcw_set_tolerance(mcw_handle* h, double rtol, int32_t max_cycles);
  * in max_cycles V-cycles, MCW_NONFINITE if u0 or the iteration is not finite. */
 mcw_status mcw_solve(mcw_handle* h, const double* u0, double* lambda, double* u, mcw_info* info);
 
-/* Solve m independent problems (an ensemble or several time steps), each on
- * its own handle, advancing them together: every multigrid phase is one
+/* Solve m independent problems (an ensemble or several time steps), each as
+ * in mcw_solve (Sec. 2, eqs. (3)-(5); Sec. 3, eqs. (6)-(7)) on its own
+ * handle, advancing them together: every multigrid phase is one
  * launch over all members that still iterate.  Arrays as in mcw_solve, one
- * per member (host arrays of device pointers); infos may be NULL or hold m
- * entries, each with the member's own status.  All handles must share one
- * device, precision and smoothing counts; the stream of hs[0] is used.
+ * per member (host arrays of device pointers); u may be NULL, and so may u[i]
+ * (that member's recovery is skipped); infos may be NULL or hold m entries,
+ * each with the member's own status.  Each member stops on its own rtol and
+ * runs at most its own max_cycles, as when solved alone.  All handles must
+ * share one device, precision and smoothing counts; the stream of hs[0] is used.
  * FP32_REFINE members with krylov = 1 run batched CG, each member stopping
  * on its own residual; FP64 handles, line-smoother handles and batches that
  * mix CG with the plain iteration are solved one member after another.
@@ -208,8 +233,12 @@ mcw_status mcw_solve(mcw_handle* h, const double* u0, double* lambda, double* u,
 mcw_status mcw_solve_batch(int32_t m, mcw_handle* const* hs, const double* const* u0,
                            double* const* lambda, double* const* u, mcw_info* infos);
 
-/* Reverse mode through the solve (transpose multigrid solve with the same
- * symmetric operator plus the adjoints of recovery and right-hand side).
+/* Reverse mode through the solve: the chain rule through eq. (3) (recovery)
+ * and the discrete eq. (5) (lambda from u0 and a).  With g_lambda = G^T
+ * A^-1 g_u, the transpose problem K mu = g_lambda has the same symmetric
+ * operator and is solved by the same multigrid iteration; then
+ * dL/du0 = g_u - 8 detJ(0) B(0) mu and dL/da_d follows from the derivatives
+ * of K and of A^-1 in eq. (3) (the coefficients are a_d^-2).
  * lambda: device N FP64, the solution of mcw_solve for this u0 and handle.
  * g_u:    device (3, nz, ny, nx) FP64, dL/du at element centres.
  * dL_du0: device (3, nz, ny, nx) FP32 output.
@@ -220,7 +249,8 @@ mcw_status mcw_adjoint(mcw_handle* h, const double* lambda, const double* g_u, f
 
 /* ---- single-step entry points (each runs one operation of the path) ---- */
 
-/* y = K x with the matrix-free element-by-element apply (2x2x2 Gauss), FP64,
+/* y = K x, K the stiffness matrix of the left side of eq. (5) (Sec. 2:
+ * 2x2x2 Gauss quadrature), by the matrix-free element-by-element apply, FP64,
  * full node vectors, no boundary conditions applied (rows of fixed nodes are
  * the unconstrained stiffness rows). */
 mcw_status mcw_apply_K(mcw_handle* h, const double* x, double* y);
@@ -232,9 +262,12 @@ mcw_status mcw_rhs(mcw_handle* h, const double* u0, double* f);
 /* u = u0 + A^-1 grad lambda at element centres (eq. (3)). */
 mcw_status mcw_recover(mcw_handle* h, const double* u0, const double* lambda, double* u);
 
-/* Weak divergence D of u0 + A^-1 grad lambda (each term with its own
- * quadrature) at all nodes (0 at fixed nodes), and rel = ||D|| / ||D0|| over
- * the free nodes, D0 the u0 term (host double, may be NULL). */
+/* Weak divergence D of u0 + A^-1 grad lambda: the constraint div u = 0 of
+ * eq. (1) tested with every free hat function, i.e. eq. (5) moved to one side
+ * (each term with its own quadrature, Sec. 2), at all nodes (0 at fixed
+ * nodes), and rel = ||D|| / ||D0|| over the free nodes, D0 the u0 term (host
+ * double, may be NULL).  D = -(f - K lambda), so rel equals the relative
+ * residual of the solve. */
 mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda, double* D,
                           double* rel);
 
@@ -258,19 +291,23 @@ typedef struct {
   const double* wind;    /* device, (3, nl, ncy, ncx): wind components at the levels */
 } mcw_coarse_wind;
 
-/* u0 (device, (3, nz, ny, nx)) at the element centres from the coarse wind:
+/* The atmospheric model's wind brought to the fire grid, the input u0 of
+ * eq. (1) (Sec. 1 places the solve after this step).
+ * u0 (device, (3, nz, ny, nx)) at the element centres from the coarse wind:
  * at each centre, the wind of the four coarse columns around it (bilinear
  * weights; positions outside the column grid take its edge) at the centre's
  * height above ground.  MCW_INVALID_ARG if the level heights do not increase
  * or do not start above z0. */
 mcw_status mcw_interp_wind(mcw_handle* h, const mcw_coarse_wind* cw, double* u0);
 
-/* uv (device, (2, ny, nx)): the horizontal wind u[0], u[1] (device,
+/* The fire model's read-out of the solved wind (Sec. 1).
+ * uv (device, (2, ny, nx)): the horizontal wind u[0], u[1] (device,
  * (3, nz, ny, nx), element centres) at `height` > 0 above the ground over
  * each element column, by the vertical rule above on the column's centres. */
 mcw_status mcw_surface_wind(mcw_handle* h, const double* u, double height, double z0, double* uv);
 
-/* Number of levels, and the dimensions of level l (host int32[3]: nx, ny, nz),
+/* The hierarchy of Sec. 3 (coarsening rule of its last paragraph).
+ * Number of levels, and the dimensions of level l (host int32[3]: nx, ny, nz),
  * whether it coarsens horizontally towards level l+1 (host int32, may be NULL)
  * and its kept node planes (host int32[nz+1], may be NULL; count written to
  * *n_keep). */
@@ -278,14 +315,18 @@ int32_t mcw_num_levels(const mcw_handle* h);
 mcw_status mcw_level_info(const mcw_handle* h, int32_t l, int32_t dims[3], int32_t* coarsen_h,
                           int32_t* keep_z, int32_t* n_keep);
 
-/* Copy the 27-point stencil of level l into out: device, 27 x N_l, entry
+/* The operator of level l: K of eq. (5) on level 0, K_c = P^T K P of eq. (7)
+ * on the coarse levels.
+ * Copy the 27-point stencil of level l into out: device, 27 x N_l, entry
  * o*N_l + n holds K[n, n + offset(o)] with o = (di+1) + 3(dj+1) + 9(dk+1), in
  * natural node order.  prec = MCW_FP64 gives the FP64 operator (available in
  * FP64 handles; for FP32_REFINE handles only level 0, recomputed), MCW_FP32_REFINE the
  * FP32 copy used by the V-cycles (out is then float*). */
 mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out);
 
-/* |sweeps| Gauss-Seidel sweeps on level l in the handle's precision of the
+/* The smoother of Sec. 3 (vertical Gauss-Seidel sweeps in four horizontal
+ * red-black groups).
+ * |sweeps| Gauss-Seidel sweeps on level l in the handle's precision of the
  * V-cycle (double* for MCW_FP64 handles, float* for MCW_FP32_REFINE): x in/out,
  * f in, level-sized node vectors.  sweeps > 0: the smoother of Sec. 3 (colours
  * (0,0),(1,0),(0,1),(1,1), each column bottom-up); sweeps < 0: the reverse
@@ -293,19 +334,24 @@ mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out);
  * |sweeps| <= 1000. */
 mcw_status mcw_smooth(mcw_handle* h, int32_t l, void* x, const void* f, int32_t sweeps);
 
-/* r = f - K_l x at free nodes, 0 at fixed nodes (V-cycle precision). */
+/* r = f - K_l x at free nodes, 0 at fixed nodes (V-cycle precision): the
+ * residual whose restriction is the coarse right-hand side of eq. (7). */
 mcw_status mcw_residual(mcw_handle* h, int32_t l, const void* x, const void* f, void* r);
 
-/* rc = P_l^T r (level l+1 vector, 0 at fixed coarse nodes). */
+/* rc = P_l^T r (level l+1 vector, 0 at fixed coarse nodes): f_c of eq. (7),
+ * P the regular-grid linear interpolation of Sec. 3. */
 mcw_status mcw_restrict(mcw_handle* h, int32_t l, const void* r, void* rc);
 
-/* x += P_l e (x level l, e level l+1). */
+/* x += P_l e (x level l, e level l+1): the correction step of eq. (7). */
 mcw_status mcw_prolong(mcw_handle* h, int32_t l, const void* e, void* x);
 
-/* e = K_L^-1 r on the coarsest level (V-cycle precision, FP64 arithmetic). */
+/* e = K_L^-1 r on the coarsest level (V-cycle precision, FP64 arithmetic):
+ * K_c u_c = f_c of eq. (7) solved by a direct method (Sec. 3). */
 mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e);
 
-/* One V-cycle on level 0 with x in/out, f in (V-cycle precision). */
+/* One V-cycle on level 0 with x in/out, f in (V-cycle precision): smoothing,
+ * the coarse-grid correction of eqs. (6)-(7) applied recursively, smoothing
+ * (Sec. 3). */
 mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
 
 /* Run `reps` launches of one multigrid kernel on level l's own buffers (their

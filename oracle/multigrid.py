@@ -19,12 +19,16 @@ CPU-baseline leg; never by the product path.
   the vertical-to-horizontal coupling ratio is r = a_3 h_3 / (a_h h_h) for
   the assembled operator (coefficient a_d^{-2}), or the printed
   h_3 / (h_1 a_3) with rule="literal"; coarsen horizontally iff the ratio of
-  the bottom layer exceeds 1/3; then, with the updated horizontal spacing,
-  walk the layers from the ground up and merge layer k with layer k+1 iff
-  the ratio of layer k is below 3 (an unpaired top layer stays).  rule="full"
-  is the base method: coarsen every direction.  Stop when the free unknowns
-  fit the direct solver, or nothing coarsens; if nothing coarsens while the
-  grid is still too large, coarsen horizontally anyway.
+  the bottom layer exceeds 1/3; then walk the layers from the ground up and
+  merge layer k with layer k+1 iff the ratio of layer k is below 3 (an
+  unpaired top layer stays).  The layer test takes h_h of the level being
+  coarsened (spacing="level", the default), so that both thresholds bound
+  the coupling anisotropy of the grid the smoother runs on by 9; the paper
+  prints the spacing after the horizontal step (spacing="coarsened"), which
+  lets a merged pair reach anisotropy 36.  rule="full" is the base method:
+  coarsen every direction.  Stop when the free unknowns fit the direct
+  solver, or nothing coarsens; if nothing coarsens while the grid is still
+  too large, coarsen horizontally anyway.
 * Beyond the paper: the symmetric V-cycle (post-smoothing in the reverse
   order) and conjugate gradients preconditioned by it, the textbook method
   (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1); and the
@@ -43,6 +47,7 @@ import scipy.sparse.linalg as spla
 from . import fem
 
 RULES = ("operator", "literal", "full")
+SPACINGS = ("level", "coarsened")
 COLOURS = ((0, 0), (1, 0), (0, 1), (1, 1))
 
 
@@ -71,9 +76,13 @@ def n_free(nx, ny, nz, gamma):
     return int(fem.free_mask(nx, ny, nz, gamma).sum())
 
 
-def decide(X, Y, Z, a, rule, gamma, coarse_max):
+def decide(X, Y, Z, a, rule, gamma, coarse_max, spacing="level"):
     """Coarsening of one level: (coarsen_horizontally, kept node planes) or None
-    when this level is the coarsest."""
+    when this level is the coarsest.  `spacing` is the horizontal spacing the
+    layer test compares with: the level's own ("level") or the one after the
+    horizontal step ("coarsened")."""
+    if spacing not in SPACINGS:
+        raise ValueError(spacing)
     nx, ny, nz = fem.dims_of(X)
     if n_free(nx, ny, nz, gamma) <= coarse_max:
         return None
@@ -87,7 +96,7 @@ def decide(X, Y, Z, a, rule, gamma, coarse_max):
             keep.append(nz)
     else:
         ch = can_h and coupling_ratio(h3[0], hh, a, rule) > 1.0 / 3.0
-        hh2 = 2.0 * hh if ch else hh
+        hh2 = 2.0 * hh if (ch and spacing == "coarsened") else hh
         keep = [0]
         k = 0
         while k < nz:
@@ -148,14 +157,15 @@ class Level:
         return self.nx, self.ny, self.nz
 
 
-def build_hierarchy(X, Y, Z, a, gamma=1, rule="operator", coarse_max=1024, max_levels=40):
+def build_hierarchy(X, Y, Z, a, gamma=1, rule="operator", coarse_max=1024, max_levels=40,
+                    spacing="level"):
     """Levels from fine to coarse, with P and K_c = P^T K P at each step."""
     a = np.asarray(a, dtype=np.float64)
     K = fem.assemble_stiffness(X, Y, Z, a)
     levels = [Level(X, Y, Z, K, gamma)]
     while len(levels) < max_levels:
         L = levels[-1]
-        d = decide(L.X, L.Y, L.Z, a, rule, gamma, coarse_max)
+        d = decide(L.X, L.Y, L.Z, a, rule, gamma, coarse_max, spacing)
         if d is None:
             break
         ch, keep_z = d

@@ -328,7 +328,9 @@ struct mcw_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  mcw_options opt{};
+  mcw_options opt{};         // opt.tune_cache is cleared; the path is kept below
+  std::string tune_cache;    // the autotuner's cache file (tune_cache_set: given in the options)
+  bool tune_cache_set = false;
   mcw::Dims d{};
   mcw::Faces faces{};
   double a[3]{};
@@ -356,6 +358,9 @@ struct mcw_handle {
   mcw::DevBuf kr, kz, kp, kq, ke;
   hipGraphExec_t kgraph = nullptr;  // one CG step
   bool kgraph_ready = false;
+  // V-cycle rate measured at set-up (FP32 refinement with the plain iteration;
+  // 0 = not measured): the first cycle count of every solve is chosen from it
+  double rho_setup = 0.0;
   std::string last_error;
 };
 
@@ -448,6 +453,8 @@ template <class T>
 void launch_relayout(const Dims& d, const T* src, T* dst, bool to_split, hipStream_t s);
 void launch_axpy64(size_t n, double alpha, const double* x, double* y, hipStream_t s);
 void launch_zero_fixed(const Dims& d, const Faces& fc, double* v, hipStream_t s);
+// p[i] = pseudo-random values in [-1, 1), a fixed function of i and seed.
+void launch_hash_fill(double* p, size_t n, unsigned long long seed, hipStream_t s);
 void launch_sum_partials(const double* partials, size_t n_part, int width, double* out,
                          hipStream_t s);
 

@@ -1054,6 +1054,20 @@ __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, size_t n, 
     p[i] = v;
 }
 
+// p[i] = a pseudo-random value in [-1, 1): the splitmix64 finaliser of i + seed
+// (Steele, Lea and Flood, "Fast splittable pseudorandom number generators").
+__global__ __launch_bounds__(256) void hash_fill_kernel(double* __restrict__ p, size_t n,
+                                                        unsigned long long seed) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)i + seed * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void fill_batched(WorkList W) {
   MCW_BATCHED_LOOP(VecJob, fill_body<T>)
@@ -1630,6 +1644,11 @@ void launch_update_lambda(const Dims& d, const float* e, const double* scale, do
   VecJob V = vec_job(lam, e, d.N(), scale);
   V.NX = d.NX();
   update_kernel<<<V.nblocks, 256, 0, s>>>(V);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_hash_fill(double* p, size_t n, unsigned long long seed, hipStream_t s) {
+  hash_fill_kernel<<<grid_stride_blocks(n), 256, 0, s>>>(p, n, seed);
   MCW_CHECK_LAUNCH();
 }
 

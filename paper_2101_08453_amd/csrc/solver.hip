@@ -144,7 +144,7 @@ bool decide(const mcw_handle& h, const Dims& d, const Faces& fc, double h1, doub
     keep_z = keep_every_other(d.nz);
   } else {
     ch = can_h && ratio(h3[0], hh) > 1.0 / 3.0;
-    const double hh2 = ch ? 2.0 * hh : hh;
+    const double hh2 = (ch && h.opt.merge_spacing == MCW_MERGE_COARSENED_SPACING) ? 2.0 * hh : hh;
     keep_z.push_back(0);
     int k = 0;
     while (k < d.nz) {
@@ -460,6 +460,65 @@ int inner_steps(double target, double rho, int cap) {
   return std::max(1, std::min(m, cap));
 }
 
+// Cycles of a refinement step before the handle's V-cycle rate is known: the
+// FP64 residual after them measures it.
+constexpr int kProbeCycles = 3;
+
+// Cycles of the next FP32 refinement step at relative residual rel: enough to
+// reach the tolerance at the rate rho (0 = not measured yet), but no further
+// than the FP32 operator resolves.  *aimed_floor tells whether that floor, not
+// the tolerance, set the target.
+int step_cycles(const mcw_handle& h, double rho, double rel, bool* aimed_floor) {
+  const double floor = inner_floor(h);
+  *aimed_floor = h.opt.rtol / rel <= floor;
+  if (h.opt.inner_cycles > 0) return h.opt.inner_cycles;
+  if (!(rho > 0.0)) return kProbeCycles;
+  return inner_steps(std::max(h.opt.rtol / rel, floor), rho, kMaxInnerCycles);
+}
+
+// The rate after a step of m cycles that reduced the FP64 residual by red.  A
+// step aimed at the FP32 floor may have been limited by it rather than by the
+// cycle, so its reduction can only raise a known estimate.
+double update_rate(double rho, double red, int m, bool aimed_floor) {
+  const double r = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / m)));
+  if (!(rho > 0.0) || !aimed_floor || r > rho) return r;
+  return rho;
+}
+
+// The FP32 V-cycle's rate on the handle's operator: from a fixed pseudo-random
+// right-hand side and x = 0, the FP32 residual norm after the first and after
+// the fourth cycle, (r4 / r1)^(1/3).  Four cycles keep the reduction well above
+// what the FP32 (or FP16) operator resolves at the rates met here.  Measured
+// once at set-up, so that every solve on the handle runs the same cycle
+// schedule for the same input.
+constexpr int kRateCycles = 4;
+
+double measure_rate(mcw_handle& h) {
+  if (h.levels.size() < 2) return 0.02;  // one level: the cycle is the direct solve
+  Level& L0 = h.levels[0];
+  const size_t N = h.d.N();
+  launch_hash_fill(h.r64.as<double>(), N, 0x6d63776eull, h.stream);
+  h.host_scalars[7] = 1.0;
+  double* scale_dev = h.scalars.as<double>() + 7;
+  MCW_HIP(hipMemcpyAsync(scale_dev, &h.host_scalars[7], sizeof(double), hipMemcpyHostToDevice,
+                         h.stream));
+  launch_scale_to_f32(h.d, h.r64.as<double>(), scale_dev, L0.f.as<float>(), h.stream);
+  launch_fill<float>(L0.x.as<float>(), N, 0.f, h.stream);
+  double rn[2] = {0.0, 0.0};
+  for (int c = 1; c <= kRateCycles; ++c) {
+    vcycle_f32(h);
+    if (c != 1 && c != kRateCycles) continue;
+    size_t np = 0;
+    launch_residual<float>(L0.d, h.faces, stencil_of<float>(L0), L0.x.as<float>(), L0.f.as<float>(),
+                           L0.r.as<float>(), h.partials.as<double>(), &np, h.stream, L0.by_res,
+                           h.n_partials);
+    reduce_to_host(h, np, 1, &rn[c == 1 ? 0 : 1]);
+  }
+  if (!(rn[0] > 0.0) || !std::isfinite(rn[1])) return 0.0;
+  const double r = std::pow(std::sqrt(rn[1] / rn[0]), 1.0 / (kRateCycles - 1));
+  return std::min(0.95, std::max(0.02, r));
+}
+
 // ---------------------------------------------------------------- solve drivers
 
 struct Progress {
@@ -517,9 +576,11 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     launch_relayout<double>(h.d, x0, lam, false, h.stream);
     return st;
   }
-  // FP32 V-cycles inside FP64 iterative refinement
-  double rho_est = 0.3, prev_rel = -1.0;
+  // FP32 V-cycles inside FP64 iterative refinement; the V-cycle rate measured
+  // at set-up sets the first cycle count, the solve's own steps the later ones
+  double rho_est = h.rho_setup, prev_rel = -1.0;
   int prev_m = 0, stall = 0;
+  bool prev_floor = false;
   const double nfree = (double)std::max<size_t>(free_count(h.d, h.faces), 1);
   for (;;) {
     MCW_HIP(hipEventRecord(h.ev[4], h.stream));
@@ -534,23 +595,21 @@ mcw_status iterate(mcw_handle& h, double* lam, double fnorm, Progress& pg) {
     ++pg.outer;
     logf(h, "refine step %d after %d cycles  rel residual %.3e", pg.outer, pg.cycles, pg.rel);
     if (!std::isfinite(pg.rel)) return MCW_NONFINITE;
+    if (prev_rel > 0.0 && prev_m > 0 && !h.opt.krylov)
+      rho_est = update_rate(rho_est, pg.rel / prev_rel, prev_m, prev_floor);
     if (pg.rel <= tol) return MCW_OK;
     if (pg.cycles >= h.opt.max_cycles) return MCW_NOT_CONVERGED;
     if (prev_rel > 0.0 && prev_m > 0) {
-      const double red = pg.rel / prev_rel;
-      if (red > 0.95) {
+      if (pg.rel / prev_rel > 0.95) {
         if (++stall >= 3) return MCW_NOT_CONVERGED;
       } else {
         stall = 0;
       }
-      rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / prev_m)));
     }
     // reduce to the tolerance in one step, but not below what FP32 can resolve.
     // (Aiming lower, at half the tolerance, trades a refinement step of one FP64
     // residual for an extra V-cycle, which costs about four times as much.)
-    int m = h.opt.inner_cycles > 0
-                ? h.opt.inner_cycles
-                : inner_steps(std::max(tol / pg.rel, inner_floor(h)), rho_est, kMaxInnerCycles);
+    int m = step_cycles(h, rho_est, pg.rel, &prev_floor);
     m = std::min(m, h.opt.max_cycles - pg.cycles);
     // scale the residual by a power of two to O(1) before rounding it to FP32
     const double rms = std::sqrt(rr / nfree);
@@ -655,9 +714,12 @@ mcw_status solve_impl(mcw_handle& h, const double* u0, double* lam, double* u, m
 // Cache of tuned tile rows, one `"key": rows` pair per line of a JSON object.
 class TuneCache {
  public:
-  TuneCache() {
+  explicit TuneCache(const std::string* given) {
     const char* env = std::getenv("MCW_TUNE_CACHE");
-    if (env && *env) {
+    if (given) {
+      path_ = *given;  // "" = no cache
+      if (path_.empty()) return;
+    } else if (env && *env) {
       path_ = env;
     } else if (const char* home = std::getenv("HOME")) {
       const std::string dir = std::string(home) + "/.cache/mcwind";
@@ -800,7 +862,7 @@ void autotune_levels(mcw_handle& h) {
   hipDeviceProp_t prop;
   MCW_HIP(hipGetDeviceProperties(&prop, h.device));
   const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
-  TuneCache cache;
+  TuneCache cache(h.tune_cache_set ? &h.tune_cache : nullptr);
   // colour pass: 0 = fused two-colour pass (one block per row), or 1, 2, 4 rows
   // of 64 columns per block of the four separate passes; residual: 1, 2, 4 rows
   const std::vector<int> cand_gs = {0, 1, 2, 4}, cand_res = {1, 2, 4};
@@ -864,7 +926,7 @@ void autotune_levels(mcw_handle& h) {
 
 // ---------------------------------------------------------------- set-up
 
-void validate(const mcw_grid_desc* g, const mcw_options& o) {
+void validate_grid(const mcw_grid_desc* g) {
   if (!g) Fail::arg("grid descriptor is null");
   if (!g->X || !g->Y || !g->Z) Fail::arg("node coordinate arrays must be non-null");
   if (g->nx < 2 || g->ny < 2 || g->nz < 1) Fail::arg("need nx >= 2, ny >= 2, nz >= 1");
@@ -875,6 +937,10 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
   for (int d = 0; d < 3; ++d)
     if (!(g->a[d] > 0.0) || !std::isfinite(g->a[d])) Fail::arg("penalty constants must be finite and > 0");
   if (g->gamma_faces > 63u) Fail::arg("gamma_faces has bits beyond the six faces");
+}
+
+void validate(const mcw_grid_desc* g, const mcw_options& o) {
+  validate_grid(g);
   if (o.precision != MCW_FP64 && o.precision != MCW_FP32_REFINE) Fail::arg("bad precision");
   if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) Fail::arg("rtol must be in (0, 1)");
   if (o.max_cycles < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post < 1)
@@ -887,6 +953,8 @@ void validate(const mcw_grid_desc* g, const mcw_options& o) {
   if (o.stencil_fp16 != 0 && o.stencil_fp16 != 1) Fail::arg("stencil_fp16 must be 0 or 1");
   if (o.stencil_fp16 && o.precision != MCW_FP32_REFINE)
     Fail::arg("stencil_fp16 needs precision FP32_REFINE");
+  if (o.merge_spacing != MCW_MERGE_LEVEL_SPACING && o.merge_spacing != MCW_MERGE_COARSENED_SPACING)
+    Fail::arg("bad merge_spacing");
 }
 
 void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, mcw_handle& h) {
@@ -894,6 +962,9 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
   if (g->gamma_faces == 63u)
     throw Error{MCW_SINGULAR, "Gamma covers every face: lambda is only defined up to a constant"};
   h.opt = opt;
+  h.tune_cache_set = opt.tune_cache != nullptr;
+  if (h.tune_cache_set) h.tune_cache = opt.tune_cache;
+  h.opt.tune_cache = nullptr;  // the caller's string need not outlive this call
   MCW_HIP(hipGetDevice(&h.device));
   h.stream = static_cast<hipStream_t>(stream);
   if (!h.stream) {
@@ -1058,6 +1129,7 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
     if (f32) autotune_levels<float>(h);
     else autotune_levels<double>(h);
   }
+  if (f32 && !opt.krylov) h.rho_setup = measure_rate(h);
   MCW_HIP(hipStreamSynchronize(h.stream));
   if (opt.verbose) {
     for (size_t l = 0; l < h.levels.size(); ++l) {
@@ -1065,7 +1137,7 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
       logf(h, "level %zu: %d x %d x %d elements, h1 %.3g, h3[0] %.3g, coarsen_h %d, planes kept %zu", l,
            L.d.nx, L.d.ny, L.d.nz, L.h1, L.h3.empty() ? 0.0 : L.h3[0], L.coarsen_h, L.keep_z.size());
     }
-    logf(h, "coarsest free unknowns %d", h.n_coarse);
+    logf(h, "coarsest free unknowns %d; V-cycle rate at set-up %.3f", h.n_coarse, h.rho_setup);
   }
 }
 
@@ -1181,8 +1253,8 @@ void vcycle_t(mcw_handle& h, T* x, const T* f) {
 // Per-member state of the refinement loop (mirrors iterate()).
 struct MemberState {
   mcw_status st = MCW_OK;
-  bool active = false;
-  double fnorm = 0.0, rel = 0.0, prev_rel = -1.0, rho_est = 0.3;
+  bool active = false, prev_floor = false;
+  double fnorm = 0.0, rel = 0.0, prev_rel = -1.0, rho_est = 0.0;
   int outer = 0, cycles = 0, prev_m = 0, stall = 0;
   std::vector<double> hist;
 };
@@ -1407,6 +1479,7 @@ class Batch {
     std::memcpy(&host_[s2_off_], s2_jobs_.data(), s2_jobs_.size() * sizeof(SumJob));
     std::memset(&host_[zero_slot_], 0, sizeof(double));
     std::vector<MemberState> ms(m_);
+    for (int i = 0; i < m_; ++i) ms[i].rho_est = hs_[i]->rho_setup;
     set_active(std::vector<int>(m_, 1));
     upload();
 
@@ -1427,9 +1500,8 @@ class Batch {
       }
     }
     MCW_HIP(hipEventRecord(h0.ev[1], s_));
-    const double tol = h0.opt.rtol;
     std::vector<double> cg_stop2(m_, 0.0);
-    std::vector<int> cg_mmax(m_, 0);
+    std::vector<int> cg_mmax(m_, 0), want_of(m_, 0);
     for (;;) {
       set_active(act);
       upload_active();
@@ -1441,28 +1513,27 @@ class Batch {
         MemberState& S = ms[i];
         if (!S.active) continue;
         mcw_handle& h = *hs_[i];
+        const double tol = h.opt.rtol;  // each member stops on its own tolerance
         const double rr = host_sums_[4 * i];
         S.rel = std::sqrt(rr) / S.fnorm;
         S.hist.push_back(S.rel);
         ++S.outer;
+        if (std::isfinite(S.rel) && S.prev_rel > 0.0 && S.prev_m > 0 && !krylov_)
+          S.rho_est = update_rate(S.rho_est, S.rel / S.prev_rel, S.prev_m, S.prev_floor);
         if (!std::isfinite(S.rel)) { S.st = MCW_NONFINITE; S.active = false; }
         else if (S.rel <= tol) { S.active = false; }
         else if (S.cycles >= h.opt.max_cycles) { S.st = MCW_NOT_CONVERGED; S.active = false; }
         if (S.active && S.prev_rel > 0.0 && S.prev_m > 0) {
-          const double red = S.rel / S.prev_rel;
-          if (red > 0.95) {
+          if (S.rel / S.prev_rel > 0.95) {
             if (++S.stall >= 3) { S.st = MCW_NOT_CONVERGED; S.active = false; }
           } else {
             S.stall = 0;
           }
-          S.rho_est = std::min(0.95, std::max(0.02, std::pow(std::max(red, 1e-300), 1.0 / S.prev_m)));
         }
         if (!S.active) continue;
-        int mi = h.opt.inner_cycles;
-        if (mi <= 0) {
-          mi = inner_steps(std::max(tol / S.rel, inner_floor(h)), S.rho_est, kMaxInnerCycles);
-        }
+        int mi = step_cycles(h, S.rho_est, S.rel, &S.prev_floor);
         mi = std::min(mi, h.opt.max_cycles - S.cycles);
+        want_of[i] = mi;
         want = std::max(want, mi);
         const double nfree = (double)std::max<size_t>(free_count(h.d, h.faces), 1);
         const double scale = std::ldexp(1.0, -std::ilogb(std::sqrt(rr / nfree)));
@@ -1479,12 +1550,30 @@ class Batch {
                              hipMemcpyHostToDevice, s_));
       upload_active();
       launch_scale_batched(fix(sc_), s_);
-      std::vector<int> took(m_, want);
+      std::vector<int> took = want_of;
       if (krylov_) {
         took = cg_inner(act, cg_stop2, cg_mmax);
       } else {
         launch_fill_batched<float>(fix(f0_), s_);
-        for (int c = 0; c < want; ++c) vcycle();
+        // each member runs its own cycle count: it leaves the active set (read
+        // by every batched kernel) once its count is done
+        std::vector<int> a = act;
+        for (int c = 0; c < want; ++c) {
+          bool change = false;
+          for (int i = 0; i < m_; ++i)
+            if (a[i] && want_of[i] <= c) { a[i] = 0; change = true; }
+          if (change) {
+            MCW_HIP(hipStreamSynchronize(s_));  // the previous upload has read host_
+            set_active(a);
+            upload_active();
+          }
+          vcycle();
+        }
+        if (a != act) {
+          MCW_HIP(hipStreamSynchronize(s_));
+          set_active(act);
+          upload_active();
+        }
       }
       launch_update_batched(fix(up_), s_);
       for (int i = 0; i < m_; ++i)
@@ -1497,15 +1586,25 @@ class Batch {
     }
     MCW_HIP(hipEventRecord(h0.ev[2], s_));
     // recovery and divergence check for every member that has an iterate
-    std::vector<int> fin(m_, 0);
-    for (int i = 0; i < m_; ++i) fin[i] = (ms[i].st == MCW_OK || ms[i].st == MCW_NOT_CONVERGED) ? 1 : 0;
+    std::vector<int> fin(m_, 0), rec(m_, 0);
+    bool any_rec = false;
+    for (int i = 0; i < m_; ++i) {
+      fin[i] = (ms[i].st == MCW_OK || ms[i].st == MCW_NOT_CONVERGED) ? 1 : 0;
+      rec[i] = fin[i] && u && u[i] ? 1 : 0;  // a member without an output wind skips recovery
+      any_rec = any_rec || rec[i];
+    }
+    if (any_rec) {
+      set_active(rec);
+      upload_active();
+      launch_recover_batched(fix(rec_), s_);
+      MCW_HIP(hipStreamSynchronize(s_));  // the upload has read host_
+    }
     set_active(fin);
     upload_active();
-    if (u) launch_recover_batched(fix(rec_), s_);
     launch_tile_batched(M_DIV, fix(div_), s_);
     launch_sum_batched(dev<SumJob>(s2_off_), m_, s_);
     for (int i = 0; i < m_; ++i)
-      if (!fin[i] && u)
+      if (!fin[i] && u && u[i])
         MCW_HIP(hipMemcpyAsync(u[i], u0[i], 3 * (size_t)hs_[i]->d.nx * hs_[i]->d.ny * hs_[i]->d.nz *
                                                sizeof(double), hipMemcpyDeviceToDevice, s_));
     fetch_sums();
@@ -1836,6 +1935,8 @@ void mcw_default_options(mcw_options* o) {
   o->krylov = 0;
   o->smoother = MCW_SMOOTH_POINT;
   o->stencil_fp16 = 0;
+  o->merge_spacing = MCW_MERGE_LEVEL_SPACING;
+  o->tune_cache = nullptr;
 }
 
 mcw_status mcw_create(const mcw_grid_desc* g, const mcw_options* opts, void* stream,

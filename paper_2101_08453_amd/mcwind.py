@@ -28,6 +28,7 @@ FP64 = 0
 FP32_REFINE = 1
 PRECISIONS = {"fp64": FP64, "fp32_refine": FP32_REFINE}
 RULES = {"operator": 0, "literal": 1, "full": 2}
+MERGE_SPACINGS = {"level": 0, "coarsened": 1}
 SMOOTHERS = {"point": 0, "line": 1}
 MAX_LEVELS = 24
 HISTORY = 64
@@ -49,7 +50,8 @@ class Options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("autotune", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("smoother", ctypes.c_int32),
-                ("stencil_fp16", ctypes.c_int32)]
+                ("stencil_fp16", ctypes.c_int32), ("merge_spacing", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class Info(ctypes.Structure):
@@ -169,7 +171,8 @@ class Grid:
     def __init__(self, X, Y, Z, a, gamma=GAMMA_BOTTOM, precision="fp32_refine", rtol=1e-8,
                  max_cycles=200, nu_pre=2, nu_post=2, inner_cycles=0, coarsen_rule="operator",
                  coarse_direct_max=1024, use_graph=True, verbose=False, autotune=True,
-                 krylov=False, smoother="point", stencil_fp16=False):
+                 krylov=False, smoother="point", stencil_fp16=False, merge_spacing="level",
+                 tune_cache=None):
         L = lib()
         self._h = H()
         nzp, nyp, nxp = X.shape
@@ -199,6 +202,8 @@ class Grid:
         o.krylov = 1 if krylov else 0
         o.smoother = SMOOTHERS[smoother]
         o.stencil_fp16 = 1 if stencil_fp16 else 0
+        o.merge_spacing = MERGE_SPACINGS[merge_spacing]
+        o.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
         o.verbose = 1 if (verbose or os.environ.get("MCW_LOG")) else 0
         self.precision = precision
         self.vdtype = torch.float32 if precision == "fp32_refine" else torch.float64
@@ -408,16 +413,24 @@ class Grid:
 def solve_batch(grids, u0s, lams=None, want_u=True, check=True):
     """Solve several problems together (mcw_solve_batch); returns (lams, us, infos, status).
 
-    With check=False a failing member does not raise: status names the first
-    failing member's status and each member's own outcome is in its info."""
+    want_u: True / False for every member, or one bool per member (a member
+    without it gets None in us and skips recovery).  With check=False a failing
+    member does not raise: status names the first failing member's status and
+    each member's own outcome is in its info."""
     m = len(grids)
     if lams is None:
         lams = [g._node() for g in grids]
-    us = [torch.empty(g.elem_shape, dtype=torch.float64, device=g.device) for g in grids] if want_u else None
+    per = [bool(w) for w in want_u] if isinstance(want_u, (list, tuple)) else [bool(want_u)] * m
+    if len(per) != m:
+        raise ValueError("want_u needs one entry per member")
+    us = [torch.empty(g.elem_shape, dtype=torch.float64, device=g.device) if w else None
+          for g, w in zip(grids, per)]
     hs = (H * m)(*[g._h.value for g in grids])
     pu0 = (P * m)(*[_ptr(u, torch.float64, g.elem_shape, "u0").value for g, u in zip(grids, u0s)])
     pl = (P * m)(*[_ptr(l, torch.float64, g.node_shape, "lambda").value for g, l in zip(grids, lams)])
-    pu = (P * m)(*[u.data_ptr() for u in us]) if want_u else None
+    pu = (P * m)(*[u.data_ptr() if u is not None else None for u in us]) if any(per) else None
+    if not any(per):
+        us = None
     infos = (Info * m)()
     st = lib().mcw_solve_batch(m, hs, pu0, pl, pu, infos)
     if check and st != MCW_OK:
@@ -446,6 +459,10 @@ class WindSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, a, grid):
+        a_host = np.asarray(a.detach().cpu().numpy(), dtype=np.float64).reshape(-1)
+        if a_host.shape != (3,) or not np.array_equal(a_host, grid.a):
+            raise ValueError(f"a = {a_host.tolist()} differs from the grid's penalties "
+                             f"{grid.a.tolist()}: set up a Grid for these penalties")
         lam, u, info = grid.solve(u0.detach().contiguous())
         ctx.grid = grid
         ctx.save_for_backward(lam)

@@ -27,12 +27,14 @@ def cube_stencil():
 
 
 def coarsening_cases():
-    """[(rule, a, gamma, coarse_max, (X, Y, Z), (coarsen_h, kept planes))]."""
+    """[(rule, spacing, a, gamma, coarse_max, (X, Y, Z), (coarsen_h, kept planes))]."""
     cases = []
     for line in _rows("coarsening_decisions.txt"):
         lhs, rhs = line.split("|")
         t = lhs.split()
-        rule, a = t[0], [float(v) for v in t[1:4]]
+        rule, _, spacing = t[0].partition(":")
+        spacing = spacing or "level"
+        a = [float(v) for v in t[1:4]]
         dx, nx, ny, gamma, cmax = float(t[4]), int(t[5]), int(t[6]), int(t[7]), int(t[8])
         if t[9] == "geom":
             thick = float(t[10]) * float(t[11]) ** np.arange(int(t[12]))
@@ -41,5 +43,5 @@ def coarsening_cases():
         zeta = np.concatenate([[0.0], np.cumsum(thick)])
         grid = inputs.terrain_grid(np.zeros((ny + 1, nx + 1)), zeta, dx, dx)
         r = [int(v) for v in rhs.split()]
-        cases.append((rule, a, gamma, cmax, grid, (bool(r[0]), r[1:])))
+        cases.append((rule, spacing, a, gamma, cmax, grid, (bool(r[0]), r[1:])))
     return cases

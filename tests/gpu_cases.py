@@ -38,9 +38,10 @@ def system(name):
 
 
 @functools.lru_cache(maxsize=None)
-def hierarchy(name, coarse_max=1024, rule="operator"):
+def hierarchy(name, coarse_max=1024, rule="operator", spacing="level"):
     p = problem(name)
-    return mg.build_hierarchy(p.X, p.Y, p.Z, p.a, p.gamma, rule=rule, coarse_max=coarse_max)
+    return mg.build_hierarchy(p.X, p.Y, p.Z, p.a, p.gamma, rule=rule, coarse_max=coarse_max,
+                              spacing=spacing)
 
 
 @functools.lru_cache(maxsize=None)

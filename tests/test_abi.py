@@ -33,6 +33,29 @@ def test_header_declares_the_boundary():
         assert need in names
 
 
+# Calls that run an operation of the method; each must cite the passage that
+# defines it.  The rest are lifetime, error, option, tolerance and timing calls.
+OPERATIONS = ["mcw_create", "mcw_solve", "mcw_solve_batch", "mcw_adjoint", "mcw_apply_K",
+              "mcw_rhs", "mcw_recover", "mcw_divergence", "mcw_interp_wind", "mcw_surface_wind",
+              "mcw_num_levels", "mcw_level_info", "mcw_get_stencil", "mcw_smooth",
+              "mcw_residual", "mcw_restrict", "mcw_prolong", "mcw_coarse_solve", "mcw_vcycle"]
+
+
+def test_every_operation_cites_its_defining_passage():
+    """The comment block in front of each operation's declaration names a
+    section or an equation of the paper."""
+    text = open(HEADER).read()
+    for name in OPERATIONS:
+        m = re.search(r"(?m)^[A-Za-z_][\w \*]*\b" + name + r"\s*\(", text)  # the declaration
+        assert m, name
+        head = text[:m.start()].rstrip()
+        if name == "mcw_level_info":  # shares the comment of mcw_num_levels
+            head = head[:head.rfind("\n")].rstrip()
+        assert head.endswith("*/"), f"{name} has no comment block"
+        block = head[head.rfind("/*"):]
+        assert re.search(r"Sec\. \d|eqs?\. \(\d\)", block), f"{name} cites no passage"
+
+
 def test_library_exports_every_declared_symbol(lib):
     from paper_2101_08453_amd import mcwind
     for name in _declared():
@@ -49,6 +72,7 @@ def test_status_strings_and_defaults(lib):
     assert (o.nu_pre, o.nu_post, o.coarsen_rule, o.use_graph) == (2, 2, 0, 1)
     # the last fields: a layout mismatch with the header would read other values here
     assert (o.krylov, o.smoother, o.stencil_fp16) == (0, 0, 0)
+    assert o.merge_spacing == 0 and o.tune_cache is None
 
 
 def test_create_rejects_bad_arguments_on_the_host(lib):
@@ -80,6 +104,10 @@ def test_create_rejects_bad_arguments_on_the_host(lib):
     o.precision = mcwind.FP32_REFINE
     o.stencil_fp16 = 2
     assert lib.mcw_create(ctypes.byref(d), ctypes.byref(o), None, ctypes.byref(h)) == 1
+    o = mcwind.default_options()
+    o.merge_spacing = 2
+    assert lib.mcw_create(ctypes.byref(d), ctypes.byref(o), None, ctypes.byref(h)) == 1
+    assert b"merge_spacing" in lib.mcw_last_error(None)
     assert not h.value
 
 

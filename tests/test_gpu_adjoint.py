@@ -152,3 +152,15 @@ def test_c5_size_gradient_finite_differences():
             gg.close()
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - g_a[dd]) <= 1e-5 * np.abs(g_a).max()
+
+
+def test_penalties_other_than_the_grids_are_rejected():
+    """dL/da is the derivative at the grid's own penalties; a different a would
+    silently get that gradient, so WindSolve refuses it."""
+    mcwind = _mcw()
+    p, _ = _small()
+    print("[case] WindSolve with mismatched a", flush=True)
+    g, u0 = mcwind.grid_from_problem(p)
+    a = torch.tensor([1.0, 1.3, 2.5], dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(ValueError, match="penalties"):
+        mcwind.WindSolve.apply(u0, a, g)

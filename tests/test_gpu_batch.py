@@ -135,3 +135,42 @@ def test_batch_mixing_cg_and_multigrid_runs_one_after_another():
     for g, u, lam in ((g0, u0, lams[0]), (g1, u1, lams[1])):
         lam1, _, _ = g.solve(u.clone(), want_u=False)
         assert torch.equal(lam, lam1)
+
+
+def test_members_keep_their_own_tolerance_and_cycle_limit():
+    """Members of one batch with different rtol and max_cycles: each stops on
+    its own tolerance and runs at most its own cycle limit, taking the same
+    cycles as when solved alone."""
+    mcwind = _mcw()
+    probs = _members()[:3]
+    print("[case] batch with per-member rtol and max_cycles", flush=True)
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p) for p in probs])]
+    grids[0].set_tolerance(1e-5, 200)
+    grids[1].set_tolerance(1e-11, 200)
+    grids[2].set_tolerance(1e-11, 3)  # 1e-11 is out of reach in 3 cycles
+    lams, us, infos, status = mcwind.solve_batch(grids, u0s, check=False)
+    assert status == "MCW_NOT_CONVERGED"
+    assert [i["status"] for i in infos] == ["MCW_OK", "MCW_OK", "MCW_NOT_CONVERGED"]
+    assert infos[0]["rel_residual"] <= 1e-5 and infos[1]["rel_residual"] <= 1e-11
+    assert infos[2]["cycles"] <= 3
+    assert infos[0]["cycles"] < infos[1]["cycles"]
+    for g, u0, info in zip(grids, u0s, infos):
+        _, _, solo = g.solve(u0.clone(), want_u=False, check=False)
+        assert solo["cycles"] == info["cycles"] and solo["status"] == info["status"]
+
+
+def test_member_without_an_output_wind_skips_recovery():
+    """u[i] = NULL for one member: its multiplier is still solved, the others
+    get their wind."""
+    mcwind = _mcw()
+    probs = _members()[:3]
+    print("[case] batch with a NULL u member", flush=True)
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p, rtol=1e-12) for p in probs])]
+    lams, us, infos, status = mcwind.solve_batch(grids, u0s, want_u=[True, False, True])
+    assert status == "MCW_OK" and us[1] is None
+    for i, p in enumerate(probs):
+        lam_ref, u_ref, _ = osolve.solve(p, rtol=1e-14)
+        assert infos[i]["rel_residual"] <= 1e-12
+        assert gc.rel_err(lams[i].cpu().numpy(), lam_ref) < 1e-8
+        if us[i] is not None:
+            assert gc.rel_err(us[i].cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8

@@ -1,0 +1,136 @@
+"""Step-by-step parity of the FP32 V-cycle kernels that the benchmark runs
+(FP32 refinement handles, with FP32 and with FP16 stencils) against the FP64
+oracle: one Gauss-Seidel sweep forward and reverse (point and line smoother),
+the residual, and one V-cycle.
+
+The oracle works on the operator the handle holds: each level's rounded
+stencil is read back through the C ABI, turned into a sparse matrix here and
+applied in FP64, while the coarsest level keeps the FP64 Galerkin operator
+(the library's coarsest solve is FP64).  What remains is FP32 arithmetic, so
+the bound is 1e-5 relative; a permuted, stale or misplaced coefficient moves
+results by O(1)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from oracle import multigrid as mg
+from tests import gpu_cases as gc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+FORMATS = {"fp32": dict(), "fp16": dict(stencil_fp16=True)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _grid(name, fmt, **kw):
+    from paper_2101_08453_amd import mcwind
+    print(f"[case] {name} {fmt} {kw}", flush=True)
+    g, _ = mcwind.grid_from_problem(gc.problem(name), precision="fp32_refine",
+                                    coarse_direct_max=60, **FORMATS[fmt], **kw)
+    return g
+
+
+def _csr_from_stencil(st):
+    """Full-grid matrix K[n, n + offset(o)] = st[o, n] of a (27, NZ, NY, NX) stencil."""
+    NZ, NY, NX = st.shape[1:]
+    N = NX * NY * NZ
+    k, j, i = np.meshgrid(np.arange(NZ), np.arange(NY), np.arange(NX), indexing="ij")
+    rows, cols, vals = [], [], []
+    for o in range(27):
+        di, dj, dk = o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1
+        ii, jj, kk = i + di, j + dj, k + dk
+        ok = (ii >= 0) & (ii < NX) & (jj >= 0) & (jj < NY) & (kk >= 0) & (kk < NZ)
+        v = st[o].astype(np.float64)[ok]
+        rows.append((i + NX * (j + NY * k))[ok])
+        cols.append((ii + NX * (jj + NY * kk))[ok])
+        vals.append(v)
+    rows, cols, vals = (np.concatenate(a) for a in (rows, cols, vals))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def _rounded_levels(g, name):
+    """The oracle's hierarchy with every level but the coarsest carrying the
+    handle's rounded operator."""
+    levels = [L for L in gc.hierarchy(name, coarse_max=60)]
+    assert g.num_levels() == len(levels)
+    out = []
+    for l, L in enumerate(levels):
+        M = mg.Level(L.X, L.Y, L.Z, L.K_full, gc.problem(name).gamma)
+        if l + 1 < len(levels):
+            Kr = _csr_from_stencil(g.stencil(l).cpu().numpy())
+            M = mg.Level(L.X, L.Y, L.Z, Kr, gc.problem(name).gamma)
+        M.P, M.P_full, M.coarsen_h, M.keep_z = L.P, L.P_full, L.coarsen_h, L.keep_z
+        out.append(M)
+    return out
+
+
+def _vectors(L, seed):
+    rng = np.random.default_rng(seed)
+    m = L.mask.reshape(L.nz + 1, L.ny + 1, L.nx + 1)
+    return rng.standard_normal(m.shape) * m, rng.standard_normal(m.shape) * m
+
+
+def _f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("fmt", list(FORMATS))
+@pytest.mark.parametrize("smoother", ["point", "line"])
+@pytest.mark.parametrize("name", gc.CASES)
+def test_sweeps_match_the_oracle_on_the_rounded_operator(name, smoother, fmt):
+    g = _grid(name, fmt, smoother=smoother)
+    levels = _rounded_levels(g, name)
+    sweep = mg.gs_sweep_full if smoother == "point" else mg.line_sweep_full
+    for l in range(min(2, len(levels) - 1)):
+        L = levels[l]
+        for reverse in (False, True):
+            x, f = _vectors(L, 20 + l + 10 * reverse)
+            x32, f32 = x.astype(np.float32), f.astype(np.float32)
+            xg = _f32(x32)
+            g.smooth(l, xg, _f32(f32), sweeps=-1 if reverse else 1)
+            ref = sweep(L.K_full, L.mask, L.dims, x32.astype(np.float64).ravel(),
+                        f32.astype(np.float64).ravel(), reverse=reverse)
+            err = gc.rel_err(xg.cpu().numpy().ravel(), ref)
+            print(f"  level {l} reverse {reverse}: rel err {err:.1e}", flush=True)
+            assert err < TOL, f"level {l} reverse {reverse}"
+
+
+@pytest.mark.parametrize("fmt", list(FORMATS))
+@pytest.mark.parametrize("name", gc.CASES)
+def test_residual_matches_the_oracle_on_the_rounded_operator(name, fmt):
+    g = _grid(name, fmt)
+    levels = _rounded_levels(g, name)
+    for l in range(min(2, len(levels) - 1)):
+        L = levels[l]
+        x, f = _vectors(L, 40 + l)
+        x32, f32 = x.astype(np.float32), f.astype(np.float32)
+        r = g.residual(l, _f32(x32), _f32(f32)).cpu().numpy().ravel()
+        ref = np.where(L.mask, f32.astype(np.float64).ravel()
+                       - L.K_full @ x32.astype(np.float64).ravel(), 0.0)
+        err = gc.rel_err(r, ref)
+        print(f"  level {l}: rel err {err:.1e}", flush=True)
+        assert err < TOL, f"level {l}"
+
+
+@pytest.mark.parametrize("fmt", list(FORMATS))
+@pytest.mark.parametrize("name", gc.CASES)
+def test_vcycle_matches_the_oracle_on_the_rounded_operators(name, fmt):
+    g = _grid(name, fmt)
+    levels = _rounded_levels(g, name)
+    M = mg.Multigrid(levels)
+    L = levels[0]
+    x, f = _vectors(L, 60)
+    x32, f32 = x.astype(np.float32), f.astype(np.float32)
+    xg = _f32(x32)
+    g.vcycle(xg, _f32(f32))
+    ref = M.vcycle(x32.astype(np.float64).ravel()[L.free], f32.astype(np.float64).ravel()[L.free])
+    err = gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref)
+    print(f"  rel err {err:.1e}", flush=True)
+    assert err < TOL

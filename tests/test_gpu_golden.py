@@ -44,10 +44,10 @@ def test_cube_grid_stencil_equals_golden_closed_form(h):
 @pytest.mark.parametrize("case", range(len(gold.coarsening_cases())))
 def test_setup_takes_golden_coarsening_decision(case):
     mcwind = _mcw()
-    rule, a, gamma, cmax, (X, Y, Z), want = gold.coarsening_cases()[case]
-    print(f"[case] golden coarsening {case} {rule}", flush=True)
+    rule, spacing, a, gamma, cmax, (X, Y, Z), want = gold.coarsening_cases()[case]
+    print(f"[case] golden coarsening {case} {rule} {spacing}", flush=True)
     g = mcwind.Grid(_dev(X), _dev(Y), _dev(Z), a, gamma=gamma, precision="fp64",
-                    coarsen_rule=rule, coarse_direct_max=cmax)
+                    coarsen_rule=rule, merge_spacing=spacing, coarse_direct_max=cmax)
     assert g.num_levels() >= 2
     lv = g.level(0)
     assert (lv["coarsen_h"], lv["keep_z"]) == want

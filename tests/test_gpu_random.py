@@ -89,7 +89,7 @@ def test_fixed_bottom_and_top_on_two_layers():
     assert gc.rel_err(u.cpu().numpy() - u0, u_ref - u0) < 1e-8
 
 
-@pytest.mark.parametrize("rule", ["operator", "full"])
+@pytest.mark.parametrize("rule", ["operator", "full", "operator:coarsened"])
 @pytest.mark.parametrize("seed", range(16))
 def test_random_transfers_match_oracle(seed, rule):
     """Restriction P^T r and prolongation x + P e on every level of the random
@@ -100,9 +100,11 @@ def test_random_transfers_match_oracle(seed, rule):
     from paper_2101_08453_amd import mcwind
     p, opts = _case(seed)
     print(f"[case] transfers seed {seed} rule {rule}", flush=True)
-    g, _ = mcwind.grid_from_problem(p, coarsen_rule=rule, **opts)
+    rule, _, spacing = rule.partition(":")
+    spacing = spacing or "level"
+    g, _ = mcwind.grid_from_problem(p, coarsen_rule=rule, merge_spacing=spacing, **opts)
     levels = omg.build_hierarchy(p.X, p.Y, p.Z, p.a, p.gamma, rule=rule,
-                                 coarse_max=opts["coarse_direct_max"])
+                                 coarse_max=opts["coarse_direct_max"], spacing=spacing)
     assert [g.level(l)["dims"] for l in range(len(levels))] == [(L.nx, L.ny, L.nz) for L in levels]
     f32 = opts["precision"] == "fp32_refine"
     dt, tol = (torch.float32, 1e-6) if f32 else (torch.float64, 1e-14)

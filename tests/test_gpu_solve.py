@@ -56,6 +56,22 @@ def test_default_tolerance_error_is_reported_and_small(precision):
     assert info["cycles"] <= 20
 
 
+def test_refinement_runs_no_more_cycles_than_the_fp64_iteration():
+    """FP32 V-cycles inside FP64 refinement need no more V-cycles than the
+    plain FP64 iteration on the 32x32x8 grid (cold start, 1e-8): the V-cycle
+    rate measured at set-up sets the first step's cycles, the measured
+    reductions the later ones.  A second solve repeats the first exactly."""
+    p = gc.problem("c1")
+    _, _, _, i64 = _solve(p, precision="fp64")
+    g, _, _, i32 = _solve(p, precision="fp32_refine")
+    print(f"fp64 {i64['cycles']} cycles, fp32_refine {i32['cycles']} cycles, "
+          f"history {i32['history']}", flush=True)
+    assert i32["rel_residual"] <= 1e-8 and i32["cycles"] <= i64["cycles"]
+    u0 = _dev(p.u0)
+    _, _, again = g.solve(u0)
+    assert again["cycles"] == i32["cycles"] and again["history"] == i32["history"]
+
+
 def test_fp64_residual_history_matches_oracle_multigrid():
     """Same hierarchy, same Gauss-Seidel order: the GPU V-cycle is the oracle's."""
     p = gc.problem("c1")

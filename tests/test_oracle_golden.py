@@ -24,6 +24,6 @@ def test_cube_grid_stencil_equals_golden_closed_form(h):
 
 @pytest.mark.parametrize("case", range(len(gold.coarsening_cases())))
 def test_coarsening_decision_equals_golden(case):
-    rule, a, gamma, cmax, (X, Y, Z), want = gold.coarsening_cases()[case]
-    ch, keep = mg.decide(X, Y, Z, a, rule, gamma, cmax)
+    rule, spacing, a, gamma, cmax, (X, Y, Z), want = gold.coarsening_cases()[case]
+    ch, keep = mg.decide(X, Y, Z, a, rule, gamma, cmax, spacing)
     assert (bool(ch), list(keep)) == want
