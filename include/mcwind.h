@@ -271,6 +271,24 @@ mcw_status mcw_recover(mcw_handle* h, const double* u0, const double* lambda, do
 mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda, double* D,
                           double* rel);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * divergence check of mcw_divergence without a handle and without any
+ * allocation.  g describes the grid as for mcw_create, but X, Y, Z are read in
+ * place (not copied) and det J is not checked.  u0, lambda, D and rel as in
+ * mcw_divergence.  stream: a hipStream_t or NULL.  With rel non-NULL the call
+ * returns when the work is complete; with rel NULL it only enqueues the work
+ * on the stream (nothing waits, so the call can be captured).
+ * The per-block partial sums live in one fixed device array of the library,
+ * MCW_NOALLOC_SCRATCH_BYTES on every device it runs on, held until the process
+ * ends: grids of more than MCW_NOALLOC_MAX_TILES element tiles (15 x 15 node
+ * columns each, i.e. ceil((nx+1)/15) * ceil((ny+1)/15)) give MCW_INVALID_ARG.
+ * Calls that overlap on one device share that array and race. */
+#define MCW_NOALLOC_SCRATCH_BYTES (2u << 20)
+#define MCW_NOALLOC_MAX_TILES ((MCW_NOALLOC_SCRATCH_BYTES / 8u - 2u) / 2u)
+mcw_status mcw_divergence_noalloc(const mcw_grid_desc* g, const double* u0, const double* lambda,
+                                  double* D, double* rel, void* stream);
+
 /* ---- steps on either side of the solve (coupled fire-atmosphere model) ----
  * The solve takes the place of plainly interpolating the atmospheric model's
  * wind to the fire model's grid (Sec. 1).  These two calls are that

@@ -761,18 +761,40 @@ void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partia
   if (n_part) *n_part = (size_t)g.x * g.y;
 }
 
-void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
-                       double* partials, size_t* n_part) {
-  TileJob A = tile_job(h);
+size_t tile_count(const Dims& d) {
+  return (size_t)((d.NX() + TN - 1) / TN) * (size_t)((d.NY() + TN - 1) / TN);
+}
+
+void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam, double* D,
+                           double* partials, hipStream_t s) {
+  TileJob A{};
+  A.X = G.X;
+  A.Y = G.Y;
+  A.Z = G.Z;
+  A.nx = G.d.nx;
+  A.ny = G.d.ny;
+  A.nz = G.d.nz;
+  for (int d = 0; d < 3; ++d) A.c[d] = G.c[d];
+  A.faces = G.faces;
+  const dim3 g((G.d.NX() + TN - 1) / TN, (G.d.NY() + TN - 1) / TN);
+  A.gx = (int)g.x;
+  A.gy = (int)g.y;
   A.ue = u0;
   A.v = lam;
   A.out = D;
   A.partials = partials;
-  const dim3 g = tile_grid(h);
-  if (partials) need_partials(2 * (size_t)g.x * g.y, h.n_partials);
-  elem_tile_kernel<M_DIV><<<g, 256, 0, h.stream>>>(A);
+  elem_tile_kernel<M_DIV><<<g, 256, 0, s>>>(A);
   MCW_CHECK_LAUNCH();
-  if (n_part) *n_part = (size_t)g.x * g.y;
+}
+
+void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
+                       double* partials, size_t* n_part) {
+  const size_t tiles = tile_count(h.d);
+  if (partials) need_partials(2 * tiles, h.n_partials);
+  GridRef G{h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(), h.d, {h.c[0], h.c[1], h.c[2]},
+            h.faces};
+  launch_divergence_ref(G, u0, lam, D, partials, h.stream);
+  if (n_part) *n_part = tiles;
 }
 
 void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_lam, double* partials,

@@ -376,6 +376,19 @@ void launch_apply(const mcw_handle& h, const double* x, const double* f, double*
 void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partials, size_t* n_part);
 void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
                        double* partials, size_t* n_part);
+// The geometry the element-tile kernels read, without a handle: node
+// coordinates in place, dimensions, coefficients a_d^-2 and Gamma.
+struct GridRef {
+  const double *X, *Y, *Z;
+  Dims d;
+  double c[3];
+  Faces faces;
+};
+// Blocks of an element-tile launch on a grid (one partial sum per block and channel).
+size_t tile_count(const Dims& d);
+// Weak divergence with 2 partial sums per block written to partials[0 .. 2 tile_count).
+void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam, double* D,
+                           double* partials, hipStream_t s);
 void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u);
 // Steps around the solve (coupling_kernels.hip)
 bool launch_coarse_check(const mcw_handle& h, const mcw_coarse_wind& cw);

@@ -12,6 +12,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <type_traits>
 #include <sys/stat.h>
@@ -1915,6 +1916,59 @@ mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u
   return b.solve(u0, lambda, u, infos);
 }
 
+// ---------------------------------------------------------------- allocation-free divergence check
+
+// Scratch of mcw_divergence_noalloc: two partial sums per element tile, then
+// the two reduced sums.  Every block writes its own partials and the
+// reduction writes the sums, so nothing has to start at zero.  Each device
+// holds its own copy until the process ends.
+static constexpr size_t kNoAllocDoubles = MCW_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Device address of `scratch` on the current device, looked up once per device.
+// On the host the array's name is only a stand-in: kernels get this address.
+static double* noalloc_scratch() {
+  static std::mutex mu;
+  static std::array<double*, 256> ptr{};
+  int dev = 0;
+  MCW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= (int)ptr.size()) Fail::arg("device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    MCW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error{MCW_HIP_ERROR, "hipGetSymbolAddress returned no address for the scratch array"};
+    ptr[dev] = static_cast<double*>(p);
+  }
+  return ptr[dev];
+}
+
+static mcw_status divergence_noalloc_impl(const mcw_grid_desc* g, const double* u0, const double* lam,
+                                   double* D, double* rel, void* stream) {
+  validate_grid(g);
+  if (g->gamma_faces == 63u)
+    throw Error{MCW_SINGULAR, "Gamma covers every face: lambda is only defined up to a constant"};
+  if (!u0 || !lam || !D) Fail::arg("null vector");
+  const Dims d{g->nx, g->ny, g->nz};
+  const size_t tiles = tile_count(d);
+  if (tiles > MCW_NOALLOC_MAX_TILES)
+    Fail::arg("grid of " + std::to_string(tiles) + " element tiles exceeds the " +
+              std::to_string(MCW_NOALLOC_MAX_TILES) + " the fixed scratch holds");
+  double* sp = noalloc_scratch();
+  GridRef G{g->X, g->Y, g->Z, d, {}, Faces{g->gamma_faces}};
+  for (int k = 0; k < 3; ++k) G.c[k] = 1.0 / (g->a[k] * g->a[k]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_divergence_ref(G, u0, lam, D, sp, s);
+  if (rel) {
+    launch_sum_partials(sp, tiles, 2, sp + 2 * tiles, s);
+    double out[2] = {0.0, 0.0};
+    MCW_HIP(hipMemcpyAsync(out, sp + 2 * tiles, sizeof(out), hipMemcpyDeviceToHost, s));
+    MCW_HIP(hipStreamSynchronize(s));
+    *rel = out[1] > 0.0 ? std::sqrt(out[0] / out[1]) : std::sqrt(out[0]);
+  }
+  return MCW_OK;
+}
+
 // ================================================================ C ABI
 
 extern "C" {
@@ -2074,6 +2128,11 @@ mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda,
     if (rel) *rel = s[1] > 0.0 ? std::sqrt(s[0] / s[1]) : std::sqrt(s[0]);
     return MCW_OK;
   });
+}
+
+mcw_status mcw_divergence_noalloc(const mcw_grid_desc* g, const double* u0, const double* lambda,
+                                  double* D, double* rel, void* stream) {
+  return guarded(nullptr, [&] { return divergence_noalloc_impl(g, u0, lambda, D, rel, stream); });
 }
 
 mcw_status mcw_interp_wind(mcw_handle* h, const mcw_coarse_wind* cw, double* u0) {

@@ -110,6 +110,8 @@ SIGNATURES = {
     "mcw_rhs": (I32, [H, P, P]),
     "mcw_recover": (I32, [H, P, P, P]),
     "mcw_divergence": (I32, [H, P, P, P, ctypes.POINTER(ctypes.c_double)]),
+    "mcw_divergence_noalloc": (I32, [ctypes.POINTER(GridDesc), P, P, P,
+                                     ctypes.POINTER(ctypes.c_double), P]),
     "mcw_num_levels": (I32, [H]),
     "mcw_level_info": (I32, [H, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
                              ctypes.POINTER(I32), ctypes.POINTER(I32)]),
@@ -436,6 +438,32 @@ def solve_batch(grids, u0s, lams=None, want_u=True, check=True):
     if check and st != MCW_OK:
         raise MCWError(st, lib().mcw_last_error(None).decode())
     return lams, us, [infos[i].to_dict() for i in range(m)], STATUS_NAMES[st]
+
+
+def divergence_noalloc(X, Y, Z, a, u0, lam, gamma=GAMMA_BOTTOM, want_rel=True):
+    """(D, rel) by mcw_divergence_noalloc: the divergence check on a grid given by
+    its node coordinates, with no handle and no device allocation by the library
+    (D is allocated here, by torch)."""
+    nzp, nyp, nxp = X.shape
+    node = (nzp, nyp, nxp)
+    elem = (3, nzp - 1, nyp - 1, nxp - 1)
+    d = GridDesc()
+    d.nx, d.ny, d.nz = nxp - 1, nyp - 1, nzp - 1
+    d.X = _ptr(X, torch.float64, node, "X")
+    d.Y = _ptr(Y, torch.float64, node, "Y")
+    d.Z = _ptr(Z, torch.float64, node, "Z")
+    d.a[0], d.a[1], d.a[2] = (float(v) for v in a)
+    d.gamma_faces = int(gamma)
+    D = torch.empty(node, dtype=torch.float64, device=X.device)
+    rel = ctypes.c_double(float("nan"))
+    stream = ctypes.c_void_p(torch.cuda.current_stream(X.device).cuda_stream)
+    st = lib().mcw_divergence_noalloc(ctypes.byref(d), _ptr(u0, torch.float64, elem, "u0"),
+                                      _ptr(lam, torch.float64, node, "lambda"),
+                                      _ptr(D, torch.float64, node, "D"),
+                                      ctypes.byref(rel) if want_rel else None, stream)
+    if st != MCW_OK:
+        raise MCWError(st, lib().mcw_last_error(None).decode())
+    return D, (rel.value if want_rel else None)
 
 
 def grid_from_problem(prob, device="cuda", **kw):
