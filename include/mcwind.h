@@ -285,7 +285,7 @@ mcw_status mcw_divergence(mcw_handle* h, const double* u0, const double* lambda,
  * columns each, i.e. ceil((nx+1)/15) * ceil((ny+1)/15)) give MCW_INVALID_ARG.
  * Calls that overlap on one device share that array and race. */
 #define MCW_NOALLOC_SCRATCH_BYTES (2u << 20)
-#define MCW_NOALLOC_MAX_TILES ((MCW_NOALLOC_SCRATCH_BYTES / 8u - 2u) / 2u)
+#define MCW_NOALLOC_MAX_TILES ((MCW_NOALLOC_SCRATCH_BYTES / 8u - 3u) / 2u)
 mcw_status mcw_divergence_noalloc(const mcw_grid_desc* g, const double* u0, const double* lambda,
                                   double* D, double* rel, void* stream);
 

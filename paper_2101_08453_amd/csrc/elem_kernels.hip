@@ -156,6 +156,128 @@ __device__ __forceinline__ void element_apply(const double Jg[3][3][4], const do
   }
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (e = 1 - x r, r += r e), within an ulp or two of the rounded quotient; for
+// the moderate, positive det J of valid elements.
+__device__ __forceinline__ double inv_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Jacobian columns at the Gauss points times 2 (the 1/2 of gauss_jacobian left
+// out): J2[m][d][pair] = 2 dx_d/dxi_m.
+__device__ __forceinline__ void gauss_jacobian2(const double xe[3][8], double J2[3][3][4]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double e[3][4];
+    edge_diffs(xe[d], e);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      double o[4];
+      bil4(e[m], o);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) J2[m][d][p] = o[p];
+    }
+  }
+}
+
+// element_apply with J2 = 2J and the reference gradients at the Gauss points
+// also left doubled: the adjugate rows of J2 are 4r, det J2 = 8 det J, so each
+// Gauss point adds 2 * 4 * 4 / 8 = 4 times its term to the accumulators, and the
+// spread back to the nodes takes 1/8 instead of 1/2.  The 1/det comes from
+// inv_newton.  Used by the per-solve kernels (apply, residual, divergence).
+__device__ __forceinline__ void element_apply2(const double J2[3][3][4], const double v[8],
+                                               const double c[3], double y[8]) {
+  double ev[3][4], G[3][4];
+  edge_diffs(v, ev);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) bil4(ev[m], G[m]);
+  double Acc[3][4] = {};
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    const int sx = g & 1, sy = (g >> 1) & 1, sz = g >> 2;
+    GP_PAIRS(sx, sy, sz);
+    const double c0[3] = {J2[0][0][p0], J2[0][1][p0], J2[0][2][p0]};
+    const double c1[3] = {J2[1][0][p1], J2[1][1][p1], J2[1][2][p1]};
+    const double c2[3] = {J2[2][0][p2], J2[2][1][p2], J2[2][2][p2]};
+    double r[3][3];
+    const double idet = inv_newton(adjugate(c0, c1, c2, r));
+    const double g0 = G[0][p0], g1 = G[1][p1], g2 = G[2][p2];
+    double q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q[d] = c[d] * idet * (g0 * r[0][d] + g1 * r[1][d] + g2 * r[2][d]);
+    Acc[0][p0] += dot3(r[0], q);
+    Acc[1][p1] += dot3(r[1], q);
+    Acc[2][p2] += dot3(r[2], q);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double B[4];
+    bil4(Acc[m], B);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double t = 0.125 * B[p];
+      const int b = p & 1, cc = p >> 1;
+      if (m == 0) { y[1 + 2 * b + 4 * cc] += t; y[0 + 2 * b + 4 * cc] -= t; }
+      if (m == 1) { y[b + 2 + 4 * cc] += t; y[b + 4 * cc] -= t; }
+      if (m == 2) { y[b + 2 * cc + 4] += t; y[b + 2 * cc] -= t; }
+    }
+  }
+}
+
+// K_e v on a terrain-following element: the x of a node depends on i only and
+// its y on j only (columns of a structured horizontal grid), so over the
+// element dx/dxi = hx/2, dy/deta = hy/2 and only z varies.  With the Jacobian
+// columns (hx/2, 0, zx), (0, hy/2, zy), (0, 0, zz) at a Gauss point, det J =
+// hx hy zz / 4; the physical gradient w from the reference gradient g is
+// w2 = g2/zz, w0 = (g0 - zx w2)/(hx/2), w1 = (g1 - zy w2)/(hy/2); the flux is
+// q = c w; and det J times J^-1 q, which the Gauss point adds to the three
+// reference directions, is (hy zz q0, hx zz q1, hx hy q2 - hy zx q0 - hx zy q1)/4.
+// Zg and G hold the z derivatives and the reference gradients doubled (bil4 of
+// the edge differences without the 1/2), whose ratios are the same; the
+// accumulators therefore hold 4 times the terms, like element_apply2's, and
+// the spread to the nodes takes 1/8.
+__device__ __forceinline__ void element_apply_tf(const double Zg[3][4], double hx, double hy,
+                                                 double ihx2, double ihy2, const double v[8],
+                                                 const double c[3], double y[8]) {
+  double ev[3][4], G[3][4];
+  edge_diffs(v, ev);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) bil4(ev[m], G[m]);
+  const double hxy = hx * hy;
+  double Acc[3][4] = {};
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    const int sx = g & 1, sy = (g >> 1) & 1, sz = g >> 2;
+    GP_PAIRS(sx, sy, sz);
+    const double zx = Zg[0][p0], zy = Zg[1][p1], zz = Zg[2][p2];
+    const double w2 = G[2][p2] * inv_newton(zz);
+    const double q0 = c[0] * (G[0][p0] - zx * w2) * ihx2;  // ihx2 = 1/hx, G and zx doubled
+    const double q1 = c[1] * (G[1][p1] - zy * w2) * ihy2;
+    const double q2 = c[2] * w2;
+    const double t0 = hy * q0, t1 = hx * q1;
+    Acc[0][p0] += t0 * zz;
+    Acc[1][p1] += t1 * zz;
+    Acc[2][p2] += hxy * q2 - zx * t0 - zy * t1;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double B[4];
+    bil4(Acc[m], B);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double t = 0.125 * B[p];
+      const int b = p & 1, cc = p >> 1;
+      if (m == 0) { y[1 + 2 * b + 4 * cc] += t; y[0 + 2 * b + 4 * cc] -= t; }
+      if (m == 1) { y[b + 2 + 4 * cc] += t; y[b + 4 * cc] -= t; }
+      if (m == 2) { y[b + 2 * cc + 4] += t; y[b + 2 * cc] -= t; }
+    }
+  }
+}
+
 // Spread a reference-space vector w (one value per direction, at the centre)
 // to the nodes: y_a += s * sum_m sign_m(a) w_m.
 __device__ __forceinline__ void spread_centre(const double w[3], double s, double y[8]) {
@@ -284,22 +406,49 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict_
 
 constexpr int TE = 16;       // element columns per tile side
 constexpr int TN = TE - 1;   // owned node columns per tile side
+constexpr int PN = TE + 1;   // node columns per tile side that the elements touch
+constexpr int PP = PN * PN;  // nodes of one tile plane
 
 // Element loop with deterministic per-node accumulation.  A block owns a
 // TN x TN patch of node columns and evaluates the TE x TE element columns
-// touching it (one element column per thread), marching up the layers.  Each
-// element leaves its 4 lower and 4 upper corner contributions in LDS; the
-// owner of a node then sums, in a fixed order, the lower contributions of the
-// current layer and the upper contributions of the layer below.
-template <int MODE>
-__device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by) {
+// touching it (one element column per thread), marching up the layers.
+//
+// The PN x PN node values of a tile plane (coordinates, and the nodal field
+// where the mode has one) are staged in LDS, so each node is read from memory
+// once per block instead of by every element around it; the loads of plane
+// k + 2 are issued before the elements of layer k are evaluated and stored
+// after them, so their latency hides behind that work.  Each element leaves
+// its 4 lower and 4 upper corner contributions in LDS; the owner of a node sums,
+// in a fixed order, the lower contributions of the current layer, and keeps the
+// sum of the upper ones for the next plane.
+//
+// TF (terrain-following grid: x of a node depends on i only, y on j only):
+// only z and the nodal field are staged per plane, each element column takes
+// its x, y extent once, and the Gauss-point work is element_apply_tf's.
+// LDS of one block, in doubles: two staged planes, the lower and upper corner
+// contributions per channel, and the reduction slots.
+constexpr int tile_lds_doubles(int mode, bool tf) {
+  const bool nodev = mode == M_APPLY || mode == M_RESID || mode == M_DIV;
+  const int na = (tf ? 1 : 3) + (nodev ? 1 : 0), ch = mode == M_DIV ? 2 : 1;
+  return 2 * na * PP + 2 * ch * 4 * 256 + 256;
+}
+constexpr int tile_lds_max(int mode) {
+  return tile_lds_doubles(mode, false) > tile_lds_doubles(mode, true) ? tile_lds_doubles(mode, false)
+                                                                      : tile_lds_doubles(mode, true);
+}
+
+template <int MODE, bool TF>
+__device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by, double* smem) {
   constexpr int CH = (MODE == M_DIV) ? 2 : 1;
   constexpr bool NODEV = (MODE == M_APPLY || MODE == M_RESID || MODE == M_DIV);
   constexpr bool ELEMV = (MODE == M_RHS || MODE == M_DIV || MODE == M_ADJ);
   constexpr bool GAUSS = NODEV;
-  __shared__ double s_lo[CH][4][256];
-  __shared__ double s_up[2][CH][4][256];
-  __shared__ double s_red[256];
+  constexpr int NC = TF ? 1 : 3;         // staged coordinate arrays: z, or x, y, z
+  constexpr int NA = NC + (NODEV ? 1 : 0);  // and the nodal field
+  double (*s_pl)[NA][PP] = reinterpret_cast<double (*)[NA][PP]>(smem);
+  double (*s_lo)[4][256] = reinterpret_cast<double (*)[4][256]>(smem + 2 * NA * PP);
+  double (*s_up)[4][256] = reinterpret_cast<double (*)[4][256]>(smem + 2 * NA * PP + CH * 4 * 256);
+  double* s_red = smem + 2 * NA * PP + 2 * CH * 4 * 256;
 
   const int t = threadIdx.x, ex = t % TE, ey = t / TE;
   const int i0 = bx * TN, j0 = by * TN;
@@ -309,22 +458,60 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by)
   const bool own = ex >= 1 && ey >= 1 && ie <= nx && je <= ny;
   const bool colfree = own && !A.faces.x_fixed(ie, NX) && !A.faces.y_fixed(je, NY);
   const int kf = A.faces.k_first(), kl = A.faces.k_last(nz + 1);
-  const int ic = ev ? ie : 0, jc = ev ? je : 0;
   const size_t plane = (size_t)NX * NY;
   const size_t E = (size_t)nx * ny * nz;
 
-  double xl[3][4], vl[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const size_t n = (size_t)(jc + (q >> 1)) * NX + ic + (q & 1);
-    xl[0][q] = A.X[n];
-    xl[1][q] = A.Y[n];
-    xl[2][q] = A.Z[n];
-    if (NODEV) vl[q] = A.v[n];
+  // TF: the element column's x and y extent (the same on every layer)
+  double x0 = 0.0, x1 = 1.0, y0 = 0.0, y1 = 1.0, hx = 1.0, hy = 1.0, ihx = 1.0, ihy = 1.0;
+  if (TF && ev) {
+    const size_t n = (size_t)je * NX + ie;
+    x0 = A.X[n];
+    x1 = A.X[n + 1];
+    y0 = A.Y[n];
+    y1 = A.Y[n + NX];
+    hx = x1 - x0;
+    hy = y1 - y0;
+    ihx = 1.0 / hx;
+    ihy = 1.0 / hy;
   }
-  double acc[CH];
+
+  // staging: thread t loads tile node t, and t + 256 where that exists;
+  // nodes outside the grid repeat the nearest grid node (no element uses them)
+  constexpr int NH = (PP + 255) / 256;
+  size_t src[NH];
 #pragma unroll
-  for (int ch = 0; ch < CH; ++ch) acc[ch] = 0.0;
+  for (int h = 0; h < NH; ++h) {
+    const int q = min(t + 256 * h, PP - 1);
+    const int gi = min(max(i0 - 1 + q % PN, 0), nx), gj = min(max(j0 - 1 + q / PN, 0), ny);
+    src[h] = (size_t)gj * NX + gi;
+  }
+  double pre[NH][NA];
+  auto load_plane = [&](int k) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const size_t n = (size_t)k * plane + src[h];
+      if (!TF) {
+        pre[h][0] = A.X[n];
+        pre[h][1] = A.Y[n];
+      }
+      pre[h][NC - 1] = A.Z[n];
+      if (NODEV) pre[h][NA - 1] = A.v[n];
+    }
+  };
+  auto store_plane = [&](int b) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int q = t + 256 * h;
+      if (q < PP) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) s_pl[b][a][q] = pre[h][a];
+      }
+    }
+  };
+
+  double acc[CH], carry[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) acc[ch] = carry[ch] = 0.0;
 
   auto node_out = [&](int k, const double s[CH]) {
     const size_t n = (size_t)k * plane + (size_t)je * NX + ie;
@@ -346,16 +533,14 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by)
     }
   };
 
+  load_plane(0);
+  store_plane(0);
+  load_plane(1);
+  store_plane(1);
+  __syncthreads();
   for (int k = 0; k < nz; ++k) {
-    double xu[3][4], vu[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const size_t n = (size_t)(k + 1) * plane + (size_t)(jc + (q >> 1)) * NX + ic + (q & 1);
-      xu[0][q] = A.X[n];
-      xu[1][q] = A.Y[n];
-      xu[2][q] = A.Z[n];
-      if (NODEV) vu[q] = A.v[n];
-    }
+    const bool more = k + 2 <= nz;
+    if (more) load_plane(k + 2);  // in flight while the elements of layer k are evaluated
     double y[CH][8];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch)
@@ -364,19 +549,29 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by)
     if (ev) {
       double xe[3][8], ve[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          xe[d][q] = xl[d][q];
-          xe[d][q + 4] = xu[d][q];
+      for (int a = 0; a < 8; ++a) {
+        const int b = (k + (a >> 2)) & 1;
+        const int q = ex + (a & 1) + PN * (ey + ((a >> 1) & 1));
+        if (TF) {
+          xe[0][a] = (a & 1) ? x1 : x0;
+          xe[1][a] = (a & 2) ? y1 : y0;
+        } else {
+          xe[0][a] = s_pl[b][0][q];
+          xe[1][a] = s_pl[b][1][q];
         }
-        ve[q] = vl[q];
-        ve[q + 4] = vu[q];
+        xe[2][a] = s_pl[b][NC - 1][q];
+        ve[a] = NODEV ? s_pl[b][NA - 1][q] : 0.0;
       }
-      if (GAUSS) {
-        double Jg[3][3][4];
-        gauss_jacobian(xe, Jg);
-        element_apply(Jg, ve, A.c, y[0]);
+      if (GAUSS && TF) {
+        double e[3][4], Zg[3][4];
+        edge_diffs(xe[2], e);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) bil4(e[m], Zg[m]);
+        element_apply_tf(Zg, hx, hy, ihx, ihy, ve, A.c, y[0]);
+      } else if (GAUSS) {
+        double J2[3][3][4];
+        gauss_jacobian2(xe, J2);
+        element_apply2(J2, ve, A.c, y[0]);
       }
       if (ELEMV) {
         const size_t e = (size_t)k * nx * ny + (size_t)je * nx + ie;
@@ -395,45 +590,30 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by)
         }
       }
     }
-    __syncthreads();
+    __syncthreads();  // the last layer's contributions are summed and plane k is no longer read
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         s_lo[ch][q][t] = y[ch][q];
-        s_up[k & 1][ch][q][t] = y[ch][q + 4];
+        s_up[ch][q][t] = y[ch][q + 4];
       }
+    if (more) store_plane(k & 1);
     __syncthreads();
     if (own) {
-      double s[CH];
+      double sum[CH];
 #pragma unroll
       for (int ch = 0; ch < CH; ++ch) {
-        double v = s_lo[ch][3][t - TE - 1] + s_lo[ch][2][t - TE] + s_lo[ch][1][t - 1] + s_lo[ch][0][t];
-        if (k > 0) {
-          const int pb = (k - 1) & 1;
-          v += s_up[pb][ch][3][t - TE - 1] + s_up[pb][ch][2][t - TE] + s_up[pb][ch][1][t - 1] +
-               s_up[pb][ch][0][t];
-        }
-        s[ch] = v;
+        const double v = s_lo[ch][3][t - TE - 1] + s_lo[ch][2][t - TE] + s_lo[ch][1][t - 1] +
+                         s_lo[ch][0][t];
+        sum[ch] = k > 0 ? v + carry[ch] : v;
+        carry[ch] = s_up[ch][3][t - TE - 1] + s_up[ch][2][t - TE] + s_up[ch][1][t - 1] +
+                    s_up[ch][0][t];
       }
-      node_out(k, s);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) xl[d][q] = xu[d][q];
-      vl[q] = vu[q];
+      node_out(k, sum);
     }
   }
-  if (own) {
-    const int pb = (nz - 1) & 1;
-    double s[CH];
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch)
-      s[ch] = s_up[pb][ch][3][t - TE - 1] + s_up[pb][ch][2][t - TE] + s_up[pb][ch][1][t - 1] +
-              s_up[pb][ch][0][t];
-    node_out(nz, s);
-  }
+  if (own) node_out(nz, carry);
   if (A.partials) {
     const int nb = A.gx * A.gy, bid = by * A.gx + bx;
 #pragma unroll
@@ -451,13 +631,20 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by)
   __syncthreads();  // the LDS slots are reused by the next work item of a batched launch
 }
 
-template <int MODE>
+// TFM: 0 general grid, 1 terrain-following grid, 2 read from *A.tf_flag (0 =
+// terrain-following), for a caller that only knows it on the device.
+template <int MODE, int TFM>
 __global__ __launch_bounds__(256) void elem_tile_kernel(TileJob A) {
-  elem_tile_body<MODE>(A, blockIdx.x, blockIdx.y);
+  __shared__ double smem[TFM == 2 ? tile_lds_max(MODE) : tile_lds_doubles(MODE, TFM == 1)];
+  if (TFM == 1 || (TFM == 2 && *A.tf_flag == 0))
+    elem_tile_body<MODE, true>(A, blockIdx.x, blockIdx.y, smem);
+  else
+    elem_tile_body<MODE, false>(A, blockIdx.x, blockIdx.y, smem);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void elem_tile_batched(WorkList W) {
+  __shared__ double smem[tile_lds_max(MODE)];
   for (int g = blockIdx.x; g < W.total; g += gridDim.x) {
     int lo = 0, hi = W.njobs - 1;
     while (lo < hi) {
@@ -468,7 +655,22 @@ __global__ __launch_bounds__(256) void elem_tile_batched(WorkList W) {
     if (!W.active[W.member[lo]]) continue;
     const TileJob& A = static_cast<const TileJob*>(W.jobs)[lo];
     const int b = g - W.prefix[lo];
-    elem_tile_body<MODE>(A, b % A.gx, b / A.gx);
+    if (A.tf)
+      elem_tile_body<MODE, true>(A, b % A.gx, b / A.gx, smem);
+    else
+      elem_tile_body<MODE, false>(A, b % A.gx, b / A.gx, smem);
+  }
+}
+
+// Sets *flag when some node's x differs from that of node (i, 0, 0) or its y
+// from that of node (0, j, 0): then the grid is not terrain-following.
+__global__ __launch_bounds__(256) void structure_check_kernel(const double* __restrict__ X,
+                                                              const double* __restrict__ Y, int NX,
+                                                              int NY, size_t N, int* flag) {
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % NX), j = (int)((n / NX) % NY);
+    if (X[n] != X[i] || Y[n] != Y[(size_t)j * NX]) atomicOr(flag, 1);
   }
 }
 
@@ -654,6 +856,7 @@ dim3 tile_grid(const mcw_handle& h) {
 
 TileJob tile_job(const mcw_handle& h) {
   TileJob A{};
+  A.tf = h.terrain ? 1 : 0;
   A.X = h.X.as<double>();
   A.Y = h.Y.as<double>();
   A.Z = h.Z.as<double>();
@@ -741,10 +944,14 @@ void launch_apply(const mcw_handle& h, const double* x, const double* f, double*
   A.partials = partials;
   const dim3 g = tile_grid(h);
   if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
-  if (mode == 0)
-    elem_tile_kernel<M_APPLY><<<g, 256, 0, h.stream>>>(A);
+  if (mode == 0 && A.tf)
+    elem_tile_kernel<M_APPLY, 1><<<g, 256, 0, h.stream>>>(A);
+  else if (mode == 0)
+    elem_tile_kernel<M_APPLY, 0><<<g, 256, 0, h.stream>>>(A);
+  else if (A.tf)
+    elem_tile_kernel<M_RESID, 1><<<g, 256, 0, h.stream>>>(A);
   else
-    elem_tile_kernel<M_RESID><<<g, 256, 0, h.stream>>>(A);
+    elem_tile_kernel<M_RESID, 0><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
 }
@@ -756,7 +963,10 @@ void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partia
   A.partials = partials;
   const dim3 g = tile_grid(h);
   if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
-  elem_tile_kernel<M_RHS><<<g, 256, 0, h.stream>>>(A);
+  if (A.tf)
+    elem_tile_kernel<M_RHS, 1><<<g, 256, 0, h.stream>>>(A);
+  else
+    elem_tile_kernel<M_RHS, 0><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
 }
@@ -783,7 +993,22 @@ void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam
   A.v = lam;
   A.out = D;
   A.partials = partials;
-  elem_tile_kernel<M_DIV><<<g, 256, 0, s>>>(A);
+  A.tf = G.tf;
+  A.tf_flag = G.tf_flag;
+  if (G.tf_flag)
+    elem_tile_kernel<M_DIV, 2><<<g, 256, 0, s>>>(A);
+  else if (G.tf)
+    elem_tile_kernel<M_DIV, 1><<<g, 256, 0, s>>>(A);
+  else
+    elem_tile_kernel<M_DIV, 0><<<g, 256, 0, s>>>(A);
+  MCW_CHECK_LAUNCH();
+}
+
+void launch_structure_check(const double* X, const double* Y, const Dims& d, int* flag,
+                            hipStream_t s) {
+  const size_t N = d.N();
+  const unsigned blocks = (unsigned)std::min<size_t>((N + 255) / 256, 8192);
+  structure_check_kernel<<<blocks, 256, 0, s>>>(X, Y, d.NX(), d.NY(), N, flag);
   MCW_CHECK_LAUNCH();
 }
 
@@ -792,7 +1017,7 @@ void launch_divergence(const mcw_handle& h, const double* u0, const double* lam,
   const size_t tiles = tile_count(h.d);
   if (partials) need_partials(2 * tiles, h.n_partials);
   GridRef G{h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(), h.d, {h.c[0], h.c[1], h.c[2]},
-            h.faces};
+            h.faces, h.terrain ? 1 : 0, nullptr};
   launch_divergence_ref(G, u0, lam, D, partials, h.stream);
   if (n_part) *n_part = tiles;
 }
@@ -805,7 +1030,10 @@ void launch_adjoint_scatter(const mcw_handle& h, const double* g_u, double* g_la
   A.partials = partials;
   const dim3 g = tile_grid(h);
   if (partials) need_partials((size_t)g.x * g.y, h.n_partials);
-  elem_tile_kernel<M_ADJ><<<g, 256, 0, h.stream>>>(A);
+  if (A.tf)
+    elem_tile_kernel<M_ADJ, 1><<<g, 256, 0, h.stream>>>(A);
+  else
+    elem_tile_kernel<M_ADJ, 0><<<g, 256, 0, h.stream>>>(A);
   MCW_CHECK_LAUNCH();
   if (n_part) *n_part = (size_t)g.x * g.y;
 }

@@ -264,6 +264,8 @@ struct TileJob {  // element-tile kernels (matrix-free apply/residual, rhs, dive
   double c[3];
   Faces faces;
   int gx, gy;        // tile grid
+  int tf;            // 1: terrain-following grid (x depends on i only, y on j only)
+  const int* tf_flag;  // device flag (0 = terrain-following) for kernels told at run time
 };
 
 struct RecoverJob {  // u = u0 + diag(c) grad lambda at element centres
@@ -349,6 +351,7 @@ struct mcw_handle {
   size_t n_partials = 0;
   double* host_scalars = nullptr;  // pinned
   mcw::DevBuf flag;         // geometry check result
+  bool terrain = false;     // x of every node depends on i only and y on j only
   hipEvent_t ev[8]{};
   // hipGraph of one FP32 V-cycle (level vectors are fixed per handle)
   hipGraphExec_t vgraph = nullptr;
@@ -383,9 +386,15 @@ struct GridRef {
   Dims d;
   double c[3];
   Faces faces;
+  int tf;              // 1: terrain-following (x depends on i only, y on j only)
+  const int* tf_flag;  // or, when not null, a device flag that says so (0 = terrain-following)
 };
 // Blocks of an element-tile launch on a grid (one partial sum per block and channel).
 size_t tile_count(const Dims& d);
+// *flag |= 1 if some node's x differs from that of its (i, 0, 0) node or its y
+// from that of its (0, j, 0) node, i.e. the grid is not terrain-following.
+void launch_structure_check(const double* X, const double* Y, const Dims& d, int* flag,
+                            hipStream_t s);
 // Weak divergence with 2 partial sums per block written to partials[0 .. 2 tile_count).
 void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam, double* D,
                            double* partials, hipStream_t s);

@@ -1003,6 +1003,17 @@ void create_impl(const mcw_grid_desc* g, const mcw_options& opt, void* stream, m
                                       std::to_string(bad / (nx * ny)) + ")"};
   }
 
+  // terrain-following grids (x of a node depends on i only, y on j only) take
+  // the element kernels' shorter path
+  const int zero = 0;
+  MCW_HIP(hipMemcpyAsync(h.flag.p, &zero, sizeof(zero), hipMemcpyHostToDevice, h.stream));
+  launch_structure_check(h.X.as<double>(), h.Y.as<double>(), h.d, h.flag.as<int>(), h.stream);
+  int not_tf = 1;
+  MCW_HIP(hipMemcpyAsync(&not_tf, h.flag.p, sizeof(not_tf), hipMemcpyDeviceToHost, h.stream));
+  MCW_HIP(hipStreamSynchronize(h.stream));
+  h.terrain = not_tf == 0;
+  logf(h, "terrain-following grid: %s", h.terrain ? "yes" : "no");
+
   // host geometry for the coarsening decisions
   HostGeom hg;
   hg.NX0 = h.d.NX();
@@ -1918,10 +1929,11 @@ mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u
 
 // ---------------------------------------------------------------- allocation-free divergence check
 
-// Scratch of mcw_divergence_noalloc: two partial sums per element tile, then
-// the two reduced sums.  Every block writes its own partials and the
-// reduction writes the sums, so nothing has to start at zero.  Each device
-// holds its own copy until the process ends.
+// Scratch of mcw_divergence_noalloc: two partial sums per element tile, the
+// two reduced sums, and the flag of the grid-structure check.  Every block
+// writes its own partials and the reduction writes the sums; the flag is
+// cleared by a fill kernel before the check.  Each device holds its own copy
+// until the process ends.
 static constexpr size_t kNoAllocDoubles = MCW_NOALLOC_SCRATCH_BYTES / sizeof(double);
 static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
@@ -1955,9 +1967,14 @@ static mcw_status divergence_noalloc_impl(const mcw_grid_desc* g, const double* 
     Fail::arg("grid of " + std::to_string(tiles) + " element tiles exceeds the " +
               std::to_string(MCW_NOALLOC_MAX_TILES) + " the fixed scratch holds");
   double* sp = noalloc_scratch();
-  GridRef G{g->X, g->Y, g->Z, d, {}, Faces{g->gamma_faces}};
-  for (int k = 0; k < 3; ++k) G.c[k] = 1.0 / (g->a[k] * g->a[k]);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // whether the grid is terrain-following is found on the device, so that the
+  // call needs no wait: the divergence kernel reads the flag
+  int* flag = reinterpret_cast<int*>(sp + 2 * tiles + 2);
+  launch_fill<double>(sp + 2 * tiles + 2, 1, 0.0, s);
+  launch_structure_check(g->X, g->Y, d, flag, s);
+  GridRef G{g->X, g->Y, g->Z, d, {}, Faces{g->gamma_faces}, 0, flag};
+  for (int k = 0; k < 3; ++k) G.c[k] = 1.0 / (g->a[k] * g->a[k]);
   launch_divergence_ref(G, u0, lam, D, sp, s);
   if (rel) {
     launch_sum_partials(sp, tiles, 2, sp + 2 * tiles, s);

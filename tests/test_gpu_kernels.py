@@ -207,3 +207,25 @@ def test_element_inverted_only_at_a_gauss_point_is_rejected():
         mcwind.Grid(_dev(X), _dev(Y), _dev(Z), p.a)
     assert ei.value.status_name == "MCW_BAD_GEOMETRY"
     assert f"element ({bad % nx}, {(bad // nx) % ny}, {bad // (nx * ny)})" in str(ei.value)
+
+
+@pytest.mark.parametrize("name,terrain", [("ragged", True), ("tiles", True), ("distorted", False)])
+def test_terrain_following_grids_take_the_short_element_path(name, terrain, capfd):
+    """Grids whose node x depends on i only and y on j only use the element
+    kernels' terrain-following path; others the general one.  Both match the
+    assembled stiffness, the right-hand side and the divergence identity."""
+    g, u0 = _grid(name, precision="fp64", verbose=True)
+    err = capfd.readouterr().err
+    assert f"terrain-following grid: {'yes' if terrain else 'no'}" in err
+    p = gc.problem(name)
+    x = np.random.default_rng(11).standard_normal(p.X.shape)
+    y = g.apply_K(_dev(x)).cpu().numpy().ravel()
+    assert gc.rel_err(y, gc.system(name).K_full @ x.ravel()) < 1e-13
+    f = g.rhs(u0).cpu().numpy().ravel()
+    S = gc.system(name)
+    assert gc.rel_err(f, np.where(S.mask, S.f_full, 0.0)) < 1e-13
+    lam, _, _ = g.solve(u0)
+    D, rel = g.divergence(u0, lam)
+    r = (g.rhs(u0) - g.apply_K(lam)).cpu().numpy()
+    m = gc.free_mask(p)
+    assert np.abs(D.cpu().numpy() + np.where(m, r, 0.0)).max() <= 1e-12 * np.abs(f).max()
