@@ -57,6 +57,8 @@ def parse():
                     help="skip the solves with the vertical line smoother")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the solves with FP16 stencils (option stencil_fp16)")
+    ap.add_argument("--no-printed", action="store_true",
+                    help="skip the solve with the coarsened spacing in the layer test (as printed)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "rules", "configs"],
                     help="c3: one 3000x3000x15 solve; c4: 64-member ensemble in one batch; "
                          "rules: coarsening rules across penalties and layer stretching")
@@ -125,9 +127,10 @@ def kernel_table(g, stream, n_free):
     ms = timed("prolong", 4)
     b = 8.0 * N + 4.0 * Nc
     out["prolong_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
-    ms = timed("residual64", 2)
-    # coordinates (24 B), lambda, f and r (8 B each) per node; FP64 VALU bound
-    b = 48.0 * N
+    ms = timed("residual64", 4)
+    # terrain-following grid: z (8 B; x and y once per column), lambda, f and r
+    # (8 B each) per node; bound by FP64 issue, not by these bytes
+    b = 32.0 * N
     out["apply_K_matfree_f64"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
     # a plain device copy of 2 GiB (read + write), the bandwidth a simple
     # streaming kernel reaches on this GPU
@@ -259,6 +262,24 @@ def bench_c4(args):
         ms_batch = e0.elapsed_time(e1) / args.steps
         cyc = [i["cycles"] for i in infos]
         log(f"batched fp32_refine: {ms_batch:.1f} ms, cycles {min(cyc)}..{max(cyc)}, {status}")
+        # the batched colour pass over every member's finest level: one sweep is
+        # four launches; each free node's 26 FP32 off-diagonals, f, and x read
+        # and written once per sweep (116 B)
+        n_free = sum(int(np.prod([d - 1 for d in p.dims[:2]])) * p.dims[2] for p in probs)
+        mcwind.run_kernel_batch(g32, "smooth", 1)
+        ms_sweep = time_on_stream(stream, lambda: mcwind.run_kernel_batch(g32, "smooth", 8), 1) / 8
+        mcwind.run_kernel_batch(g32, "residual", 1)
+        ms_res = time_on_stream(stream, lambda: mcwind.run_kernel_batch(g32, "residual", 8), 1) / 8
+        b_sweep = 116.0 * n_free
+        b_res = 116.0 * sum(p.n_nodes for p in probs)
+        batch_roof = {"bound": "hbm", "kernel": "gs_pass_batched<float, 0> (four colour passes per sweep)",
+                      "bytes_per_launch": b_sweep / 4, "ms_per_launch": round(ms_sweep / 4, 4),
+                      "achieved": round(b_sweep / ms_sweep / 1e6, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(b_sweep / ms_sweep / 1e6 / HBM_PEAK_GBS, 4),
+                      "residual_batched_GB/s": round(b_res / ms_res / 1e6, 1),
+                      "residual_batched_ms": round(ms_res, 4)}
+        log(f"batched colour pass: {ms_sweep / 4:.3f} ms per launch, {batch_roof['achieved']:.0f} GB/s; "
+            f"batched residual {ms_res:.3f} ms, {batch_roof['residual_batched_GB/s']:.0f} GB/s")
 
         def sequential(grids):
             out = []
@@ -332,6 +353,7 @@ def bench_c4(args):
                                    "ms": round(ms_seq32, 2), "setup_s": round(setup32, 2)},
         "max_lambda_rel_diff_vs_fp64": err,
         "cycles": [min(cyc), max(cyc)],
+        "roofline": batch_roof,
         "batched_mg_pcg": {"value": round(nodes / ms_batch_cg / 1e3, 2), "ms": round(ms_batch_cg, 2),
                            "steps": [min(cyk), max(cyk)]},
         "sequential_mg_pcg": {"value": round(nodes / ms_seq_cg / 1e3, 2), "ms": round(ms_seq_cg, 2)},
@@ -616,8 +638,9 @@ def main():
 
         # the layer test of the coarsening rule with the coarsened horizontal
         # spacing, as printed, instead of the level's own
-        printed = variant("coarsened spacing in the layer test", "lambda_rel_diff_vs_multigrid",
-                          merge_spacing="coarsened")
+        printed = None if args.no_printed else variant(
+            "coarsened spacing in the layer test", "lambda_rel_diff_vs_multigrid",
+            merge_spacing="coarsened")
         # CG preconditioned with one symmetric V-cycle per step
         krylov = None if args.no_krylov else variant("mg-pcg", "lambda_rel_diff_vs_multigrid",
                                                      krylov=True)

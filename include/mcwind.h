@@ -380,6 +380,13 @@ mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
  * f - K lambda on the fine grid (l must be 0).  For timing and profiling. */
 mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps);
 
+/* Run `reps` launches of one batched phase over the finest level of m handles
+ * (as mcw_solve_batch runs it; all members take part, on their own level
+ * buffers and current contents) and wait: kernel 0 = one Gauss-Seidel sweep
+ * (four batched colour passes), 1 = the residual.  FP32_REFINE point-smoother
+ * members with equal krylov and smoothing counts.  For timing and profiling. */
+mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps);
+
 /* Tile shape used on level l by the Gauss-Seidel colour pass and by the
  * residual (host int32 outputs): rows of 64 columns per block, and for the
  * colour pass 0 when it runs fused, two colours per launch with one block per

@@ -1656,6 +1656,25 @@ class Batch {
     return first;
   }
 
+  // For timing: `reps` launches of one batched phase over every member's finest
+  // level on the members' own buffers (their current contents), all members
+  // taking part.  kernel 0: one Gauss-Seidel sweep (four batched colour
+  // passes), 1: the residual.
+  void run_fine(int kernel, int reps) {
+    set_active(std::vector<int>(m_, 1));
+    upload();
+    for (int r = 0; r < reps; ++r) {
+      if (kernel == 0) {
+        for (int c = 0; c < 4; ++c)
+          for (int f = 0; f < 2; ++f)
+            launch_gs_batched<float>(fix(gs_[0][c].w[f]), s_, by_gs_[0], false, f == 1);
+      } else {
+        for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[0].w[f]), s_, by_res_[0], f == 1);
+      }
+    }
+    MCW_HIP(hipStreamSynchronize(s_));
+  }
+
  private:
   struct Slot {
     size_t jobs = 0, prefix = 0, member = 0;
@@ -1892,6 +1911,33 @@ class Batch {
   double* host_sums_ = nullptr;
   hipGraphExec_t graph_ = nullptr;
 };
+
+void check_batch_handles(int m, mcw_handle* const* hs) {
+  for (int i = 0; i < m; ++i) {
+    if (!hs[i]) Fail::arg("batch member " + std::to_string(i) + " has a null handle");
+    if (hs[i]->device != hs[0]->device) Fail::arg("batch members must share one device");
+    if (hs[i]->opt.precision != hs[0]->opt.precision) Fail::arg("batch members must share one precision");
+    if (hs[i]->opt.nu_pre != hs[0]->opt.nu_pre || hs[i]->opt.nu_post != hs[0]->opt.nu_post)
+      Fail::arg("batch members must share nu_pre and nu_post");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) Fail::arg("a handle appears twice in the batch");
+  }
+}
+
+mcw_status run_kernel_batch_impl(int m, mcw_handle* const* hs, int kernel, int reps) {
+  if (m < 1 || !hs) Fail::arg("need at least one member");
+  if (kernel < 0 || kernel > 1 || reps < 1 || reps > 10000) Fail::arg("bad kernel or reps");
+  check_batch_handles(m, hs);
+  for (int i = 0; i < m; ++i)
+    if (hs[i]->opt.precision != MCW_FP32_REFINE || hs[i]->opt.smoother != MCW_SMOOTH_POINT ||
+        hs[i]->opt.krylov != hs[0]->opt.krylov)
+      Fail::arg("batched kernels run FP32_REFINE point-smoother members of one kind");
+  for (int i = 1; i < m; ++i) MCW_HIP(hipStreamSynchronize(hs[i]->stream));
+  Batch b(std::vector<mcw_handle*>(hs, hs + m));
+  b.build();
+  b.run_fine(kernel, reps);
+  return MCW_OK;
+}
 
 mcw_status solve_batch_impl(int m, mcw_handle* const* hs, const double* const* u0,
                             double* const* lambda, double* const* u, mcw_info* infos) {
@@ -2311,6 +2357,10 @@ mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f) {
     MCW_HIP(hipStreamSynchronize(h->stream));
     return MCW_OK;
   });
+}
+
+mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps) {
+  return guarded(nullptr, [&] { return run_kernel_batch_impl(m, hs, kernel, reps); });
 }
 
 mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps) {

@@ -174,3 +174,21 @@ def test_member_without_an_output_wind_skips_recovery():
         assert gc.rel_err(lams[i].cpu().numpy(), lam_ref) < 1e-8
         if us[i] is not None:
             assert gc.rel_err(us[i].cpu().numpy() - p.u0, u_ref - p.u0) < 1e-8
+
+
+def test_batched_kernel_timing_entry_point_leaves_solves_unchanged():
+    """mcw_run_kernel_batch launches the batched sweep and residual on the
+    members' own level buffers (scratch of the V-cycle): a batch solve after
+    it gives the same multiplier bit for bit."""
+    mcwind = _mcw()
+    probs = _members()[:3]
+    print("[case] batched kernel timing entry point", flush=True)
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p) for p in probs])]
+    lams, _, _, _ = mcwind.solve_batch(grids, u0s, want_u=False)
+    mcwind.run_kernel_batch(grids, "smooth", 3)
+    mcwind.run_kernel_batch(grids, "residual", 2)
+    lams2, _, _, _ = mcwind.solve_batch(grids, u0s, want_u=False)
+    for a, b in zip(lams, lams2):
+        assert torch.equal(a, b)
+    with pytest.raises(mcwind.MCWError):
+        mcwind.run_kernel_batch(grids, "smooth", 0)
