@@ -617,16 +617,7 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by,
   if (A.partials) {
     const int nb = A.gx * A.gy, bid = by * A.gx + bx;
 #pragma unroll
-    for (int ch = 0; ch < CH; ++ch) {
-      __syncthreads();
-      s_red[t] = acc[ch];
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) s_red[t] += s_red[t + w];
-        __syncthreads();
-      }
-      if (t == 0) A.partials[(size_t)ch * nb + bid] = s_red[0];
-    }
+    for (int ch = 0; ch < CH; ++ch) block_sum_to(acc[ch], s_red, &A.partials[(size_t)ch * nb + bid]);
   }
   __syncthreads();  // the LDS slots are reused by the next work item of a batched launch
 }
@@ -817,18 +808,8 @@ __global__ __launch_bounds__(256) void adjoint_elem_kernel(
       }
     }
   }
-  const int t = threadIdx.x;
   const int nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-  for (int d = 0; d < 3; ++d) {
-    __syncthreads();
-    s_red[t] = acc[d];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) s_red[t] += s_red[t + w];
-      __syncthreads();
-    }
-    if (t == 0) partials[(size_t)d * nb + bid] = s_red[0];
-  }
+  for (int d = 0; d < 3; ++d) block_sum_to(acc[d], s_red, &partials[(size_t)d * nb + bid]);
 }
 
 __global__ __launch_bounds__(256) void sumsq_kernel(const double* __restrict__ v, size_t n,
@@ -837,13 +818,7 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const double* __restrict__ v
   double a = 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     a += v[i] * v[i];
-  s_red[threadIdx.x] = a;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = s_red[0];
+  block_sum_to(a, s_red, &partials[blockIdx.x]);
 }
 
 dim3 tile_grid(const mcw_handle& h) {

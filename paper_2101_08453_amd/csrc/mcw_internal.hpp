@@ -65,6 +65,32 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// ---------------------------------------------------------------- reductions
+
+// Sum over the 64 lanes of a wave by a butterfly of lane exchanges (no LDS);
+// lane 0's result has a fixed order of additions.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Block-wide sum of one double per thread into *out: each wave's sum, then
+// thread 0 adds the waves' sums in wave order (deterministic).  s_red holds at
+// least one slot per wave of the block.
+__device__ __forceinline__ void block_sum_to(double v, double* s_red, double* out) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double s = s_red[0];
+    for (int w = 1; w < nw; ++w) s += s_red[w];
+    *out = s;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- stencil layout
 
 // 27-point stencils are stored per node as SW = 28 values (27 coefficients

@@ -137,17 +137,6 @@ __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njob
   return lo;
 }
 
-// Block-wide sum of one double per thread into *out (fixed tree, deterministic).
-__device__ __forceinline__ void block_sum_to(double v, double* s_red, double* out) {
-  s_red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = s_red[0];
-  __syncthreads();
-}
 
 // Run BODY(job, local block) over the work list W of a batched launch.
 #define MCW_BATCHED_LOOP(JOBT, BODY)                                            \
@@ -452,9 +441,6 @@ __global__ __launch_bounds__(256) void residual_kernel(ColJob J, double* __restr
   __shared__ double s_red[256];
   const double acc = residual_body<T, DOTX, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
   if (NORM) {
-    // blocks narrower than 256 threads: the missing lanes add zero
-    if (threadIdx.x == 0)
-      for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
     block_sum_to(acc, s_red, &partials[blockIdx.x]);
   }
 }
@@ -467,8 +453,6 @@ template <class T, int SF>
 __device__ __forceinline__ void residual_dot_item(const ColJob& J, int b) {
   __shared__ double s_red[256];
   const double acc = residual_body<T, true, SF>(J, xcd_remap(b, J.nblocks));
-  if (threadIdx.x == 0)
-    for (int t = blockDim.x; t < 256; ++t) s_red[t] = 0.0;
   block_sum_to(acc, s_red, &J.part[b]);
 }
 

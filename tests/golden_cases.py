@@ -45,3 +45,17 @@ def coarsening_cases():
         r = [int(v) for v in rhs.split()]
         cases.append((rule, spacing, a, gamma, cmax, grid, (bool(r[0]), r[1:])))
     return cases
+
+
+def c5_gradient():
+    """{"loss": L, "dL_da": [3], "directional": [20]} from c5_gradient.txt."""
+    out = {"directional": []}
+    for line in _rows("c5_gradient.txt"):
+        t = line.split()
+        if t[0] == "loss":
+            out["loss"] = float(t[1])
+        elif t[0] == "dL_da":
+            out["dL_da"] = [float(v) for v in t[1:4]]
+        elif t[0] == "dL_du0_dot_direction":
+            out["directional"].append(float(t[2]))
+    return out

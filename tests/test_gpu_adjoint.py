@@ -154,6 +154,30 @@ def test_c5_size_gradient_finite_differences():
         assert abs(fd - g_a[dd]) <= 1e-5 * np.abs(g_a).max()
 
 
+def test_c5_size_gradient_against_the_oracle():
+    """512x512x15 fractal terrain (500 m relief), elliptical fire mask: the
+    adjoint's loss, dL/da and the directional derivatives <dL/du0, d> along 20
+    seeded directions against the FP64 oracle's (tests/golden/c5_gradient.txt,
+    written by the oracle alone), at 1e-6 relative.  L is quadratic in u0 and
+    the solves run to 1e-12, so only the FP32 output of dL/du0 and the
+    reduction orders separate the two."""
+    from tests import golden_cases as gold
+    ref = gold.c5_gradient()
+    assert len(ref["directional"]) == 20
+    p = inputs.c5()
+    mask = inputs.fire_mask(512, 512, seed=55)
+    print("[case] c5 gradient against the oracle's", flush=True)
+    _, L, g_u0, g_a = _grad_gpu(p, mask, rtol=1e-12)
+    assert abs(L - ref["loss"]) <= 1e-9 * abs(ref["loss"])
+    assert np.allclose(g_a, ref["dL_da"], rtol=1e-6, atol=1e-9 * np.abs(ref["dL_da"]).max())
+    dirs = inputs.random_directions(p.u0.shape, 20, seed=56)
+    got = np.array([float(np.sum(g_u0.astype(np.float64) * d)) for d in dirs])
+    want = np.array(ref["directional"])
+    err = np.abs(got - want) / np.abs(want).max()
+    print(f"[c5] directional derivatives: max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-6
+
+
 def test_penalties_other_than_the_grids_are_rejected():
     """dL/da is the derivative at the grid's own penalties; a different a would
     silently get that gradient, so WindSolve refuses it."""
