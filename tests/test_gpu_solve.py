@@ -359,3 +359,23 @@ def test_placement_probing_and_autotune_do_not_change_results(tmp_path, monkeypa
         out.append((lam, u))
         g.close()
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("smoother", ["point", "line"])
+@pytest.mark.parametrize("precision", ["fp32_refine", "fp64"])
+def test_tall_columns_match_oracle(precision, smoother):
+    """160 layers over a small horizontal grid (the vertical march of the
+    smoothers and the element tiles over many planes; the line smoother's
+    column solve beyond what its LDS holds)."""
+    nx, ny, nz = 14, 11, 160
+    zeta = inputs.vertical_levels(nz, first=2.0, ratio=1.01)  # 2 m to 9.6 m layers, 780 m deep
+    zs = inputs.gaussian_hills(nx, ny, 30.0, 30.0, [60.0], [120.0], [200.0], [150.0])
+    X, Y, Z = inputs.terrain_grid(zs, zeta, 30.0, 30.0)
+    u0 = inputs._log_wind(nx, ny, nz, zeta, 6.0, 0.7)
+    u0 += np.random.default_rng(77).normal(0.0, 0.3, u0.shape)
+    p = inputs.Problem("tall columns", X, Y, Z, u0, np.array([1.0, 1.0, 2.0]))
+    lam_ref, u_ref, _ = osolve.solve(p, rtol=1e-14)
+    _, lam, u, info = _solve(p, precision=precision, smoother=smoother, rtol=1e-12)
+    assert info["status"] == "MCW_OK" and info["rel_residual"] <= 1e-12
+    assert gc.rel_err(lam, lam_ref) < 1e-8
+    assert gc.rel_err(u - p.u0, u_ref - p.u0) < 1e-8
