@@ -32,21 +32,31 @@ def surface_loss(u, mask):
     return L, g
 
 
-def forward(prob_X, prob_Y, prob_Z, u0, a, gamma, rtol=1e-13):
+def _solve(K, f, rtol, solver):
+    if solver is None:
+        return solve_system(K, f, rtol=rtol)[0]
+    return solver(K, f)
+
+
+def forward(prob_X, prob_Y, prob_Z, u0, a, gamma, rtol=1e-13, solver=None):
+    """solver: None for solve_system's default choice, else a callable
+    (K, f) -> x that solves K x = f to the accuracy the caller needs (a large
+    grid's Jacobi-PCG cannot reach 1e-13 in reasonable time)."""
     S = System(prob_X, prob_Y, prob_Z, u0, a, gamma)
-    x, _, _ = solve_system(S.K, S.f, rtol=rtol)
+    x = _solve(S.K, S.f, rtol, solver)
     lam = S.expand(x)
     u = fem.recover(prob_X, prob_Y, prob_Z, u0, a, lam)
     return S, lam, u
 
 
-def gradient(prob, mask, rtol=1e-13):
-    """(L, dL/du0 (3,nz,ny,nx), dL/da (3,)) for the surface loss."""
+def gradient(prob, mask, rtol=1e-13, solver=None):
+    """(L, dL/du0 (3,nz,ny,nx), dL/da (3,)) for the surface loss; `solver`
+    as in forward, used for both the forward and the transpose solve."""
     X, Y, Z = prob.X, prob.Y, prob.Z
     nx, ny, nz = prob.dims
     a = np.asarray(prob.a, dtype=np.float64)
     c = fem.penalty_coefficients(a)
-    S, lam, u = forward(X, Y, Z, prob.u0, a, prob.gamma, rtol)
+    S, lam, u = forward(X, Y, Z, prob.u0, a, prob.gamma, rtol, solver)
     L, g_u = surface_loss(u, mask)
 
     # g_lambda = G_1^T diag(c) g_u, assembled over the elements
@@ -59,7 +69,7 @@ def gradient(prob, mask, rtol=1e-13):
         B0, _ = fem.physical_gradients(fem.element_coords(X, Y, Z, ids), fem.CENTRE)
         gu = np.stack([g_u[d, k].ravel() for d in range(3)], axis=1)
         np.add.at(g_lam, ids.ravel(), np.einsum("eda,ed->ea", B0, c[None, :] * gu).ravel())
-    mu_free, _, _ = solve_system(S.K, g_lam[S.free], rtol=rtol)
+    mu_free = _solve(S.K, g_lam[S.free], rtol, solver)
     mu_full = S.expand(mu_free)
     for k in range(nz):
         ids = fem.element_node_ids(nx, ny, nz, layers=[k])
