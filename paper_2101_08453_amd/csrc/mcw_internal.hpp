@@ -240,6 +240,8 @@ struct ColJob {  // smoother colour pass, residual
   double* part;          // per-block partial sums of a batched residual with a dot product
   int h16;               // the stencil holds FP16 values scaled by 1/sc (FP32 V-cycles only)
   float sc, isc;         // sc and 1/sc; 1 for FP32 and FP64 stencils
+  void* rlast;           // forward pass of colour (1,1) ending a sweep: also write r there
+  int skip11;            // residual: colour (1,1) columns already hold r (written by rlast)
 };
 
 struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
@@ -446,9 +448,13 @@ void launch_recover_batched(const WorkList& W, hipStream_t s);
 // Multigrid kernels (templated on the V-cycle precision)
 // line_buf: null for the point smoother; for the vertical line smoother a
 // level-sized scratch vector (the elimination coefficients)
+// r_last: when given (forward sweeps only), the pass of the last colour, (1,1),
+// also writes r = f - K x on its columns, which no later pass of the sweep
+// changes; launch_residual with last_colour_done then computes only the others.
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
-                         hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr);
+                         hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr,
+                         T* r_last = nullptr);
 // preconditioned conjugate gradients; sc = device scalars {r.z, alpha, beta, r.r}
 void launch_cg_reset(double* sc, hipStream_t s);
 template <class T>
@@ -467,7 +473,8 @@ void launch_neg_apply_dot(const Dims& d, const Faces& fc, StRef st, const T* p, 
                           double* partials, size_t cap, size_t* n_part, hipStream_t s, int by);
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s, int by = 4, size_t cap = 0);
+                     double* partials, size_t* n_part, hipStream_t s, int by = 4, size_t cap = 0,
+                     bool last_colour_done = false);
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                      const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s);

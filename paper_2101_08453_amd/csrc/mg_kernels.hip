@@ -153,12 +153,32 @@ __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njob
 // top, or top to bottom for the reverse (adjoint) sweep.  Neighbour columns
 // belong to other colours and are not changed meanwhile; the value below (or
 // above) is this thread's own freshly updated one.
+// r = f - K x of a whole column, zero: a fixed column, or one that a line
+// solve has just made exact.
+template <class T>
+__device__ __forceinline__ void zero_column_r(const ColJob& J, int i, int j) {
+  T* __restrict__ rl = static_cast<T*>(J.rlast);
+  const size_t plane = (size_t)J.NX * J.NY;
+  const int own = j * J.NX + sx(i, (J.NX + 1) >> 1);
+  for (int k = 0; k < J.NZ; ++k) rl[(size_t)k * plane + own] = T(0);
+}
+
+// With J.rlast (forward passes of the last colour only) the column's residual
+// is written as well.  Right after node k is solved its residual is zero up to
+// rounding; of the later updates in the sweep only that of node k + 1 above it
+// couples to it (neighbour columns are other colours, all done before), so its
+// final residual is -a_k(above) (x_{k+1,new} - x_{k+1,old}), and the top free
+// node's is zero.  The residual kernel then skips these columns.
 template <class T, bool REV, int SF = 0>
 __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
-  if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) return;
+  T* __restrict__ rl = REV ? nullptr : static_cast<T*>(J.rlast);
+  if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
+    if (rl) zero_column_r<T>(J, i, j);
+    return;
+  }
   const int im = i > 0 ? i - 1 : i, ip = i < NX - 1 ? i + 1 : i;
   const int jm = j > 0 ? j - 1 : j, jp = j < NY - 1 ? j + 1 : j;
   const StLayout L = dev_layout(NX, NY);
@@ -168,6 +188,11 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
                        j * NX + sp, jp * NX + sm, jp * NX + s0, jp * NX + sp};
   const size_t plane = (size_t)NX * NY;
   const int kf = J.fc.k_first(), kl = J.fc.k_last(NZ);
+  if (rl) {
+    for (int k = 0; k < kf; ++k) rl[(size_t)k * plane + cols[4]] = T(0);
+    for (int k = kl; k < NZ; ++k) rl[(size_t)k * plane + cols[4]] = T(0);
+  }
+  T a_up = T(0);  // the coupling of the node below to this one
   // rolling window of the 3 x 9 neighbour values: xl the plane already passed,
   // x0 the current plane, xn the plane ahead
   T xl[9], x0[9], xn[9];
@@ -199,6 +224,10 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
       s -= a[o] * xv;
     }
     const T xnew = s / a[13];
+    if (!REV && rl) {
+      if (t > 0) rl[(size_t)(k - 1) * plane + cols[4]] = scaled<SF>(-a_up * (xnew - x0[4]), J.sc);
+      a_up = a[22];
+    }
     x[(size_t)k * plane + cols[4]] = xnew;
     x0[4] = xnew;
 #pragma unroll
@@ -306,8 +335,12 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j, T* ls
 
 template <class T, bool REV, bool LINE, int SF = 0, bool LDS = false>
 __device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j, T* ls = nullptr) {
-  if constexpr (LINE) line_column<T, SF, LDS>(J, i, j, ls, (int)blockDim.x);
-  else gs_column<T, REV, SF>(J, i, j);
+  if constexpr (LINE) {
+    line_column<T, SF, LDS>(J, i, j, ls, (int)blockDim.x);
+    if (J.rlast) zero_column_r<T>(J, i, j);
+  } else {
+    gs_column<T, REV, SF>(J, i, j);
+  }
 }
 
 // One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
@@ -392,6 +425,7 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   const int NXe = (NX + 1) >> 1;
   const int i = qx < NXe ? 2 * qx : 2 * (qx - NXe) + 1;
   const int own = j * NX + qx;
+  if (J.skip11 && (i & j & 1)) return acc;  // written by the sweep's last colour pass
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
     for (int k = 0; k < NZ; ++k) r[(size_t)k * plane + own] = T(0);
     return acc;
@@ -1186,13 +1220,15 @@ size_t line_lds_bytes(const Dims& d, const Faces& fc, int threads) {
 
 template <class T, bool LINE, int SF>
 void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
-                    hipStream_t s, int by, bool reverse) {
+                    hipStream_t s, int by, bool reverse, T* r_last) {
+  if (reverse) r_last = nullptr;
   if (by == 0) {
     // colours (0,0),(1,0) then (0,1),(1,1); reversed: (1,1),(0,1) then (1,0),(0,0)
     for (int pr = 0; pr < 2; ++pr) {
       const int c0 = reverse ? 3 - 2 * pr : 2 * pr, c1 = reverse ? c0 - 1 : c0 + 1;
       const ColJob J0 = col_job(d, fc, st, f, x, cbuf, c0, 1);
-      const ColJob J1 = col_job(d, fc, st, f, x, cbuf, c1, 1);
+      ColJob J1 = col_job(d, fc, st, f, x, cbuf, c1, 1);
+      if (c1 == 3) J1.rlast = r_last;
       if (J0.ncy <= 0) continue;
       const int cols = std::max(J0.ncx, J1.ncx);
       const int threads = std::min(fused_threads<T, LINE>(), std::max(64, (cols + 63) / 64 * 64));
@@ -1218,7 +1254,8 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
   const size_t lds = LINE ? line_lds_bytes<T>(d, fc, BX * by) : 0;
   for (int cc = 0; cc < 4; ++cc) {
     const int c = reverse ? 3 - cc : cc;
-    const ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
+    ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
+    if (c == 3) J.rlast = r_last;
     if (J.nblocks <= 0) continue;
     if constexpr (LINE) {
       if (lds) {
@@ -1241,23 +1278,23 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
 // format 1 (FP16 stencil) exists for FP32 V-cycles only
 template <class T, bool LINE>
 void smooth_sweep_t(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
-                    hipStream_t s, int by, bool reverse) {
+                    hipStream_t s, int by, bool reverse, T* r_last) {
   if constexpr (sizeof(T) == 4) {
     if (st.h16) {
-      smooth_sweep_f<T, LINE, 1>(d, fc, st, f, x, cbuf, s, by, reverse);
+      smooth_sweep_f<T, LINE, 1>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
       return;
     }
   }
-  smooth_sweep_f<T, LINE, 0>(d, fc, st, f, x, cbuf, s, by, reverse);
+  smooth_sweep_f<T, LINE, 0>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
 }
 
 template <class T>
 void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
-                         hipStream_t s, int by, bool reverse, T* line_buf) {
+                         hipStream_t s, int by, bool reverse, T* line_buf, T* r_last) {
   if (line_buf)
-    smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse);
+    smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse, r_last);
   else
-    smooth_sweep_t<T, false>(d, fc, st, f, x, nullptr, s, by, reverse);
+    smooth_sweep_t<T, false>(d, fc, st, f, x, nullptr, s, by, reverse, r_last);
 }
 
 // ---- conjugate gradients on level-0 vectors, coefficients kept on the device
@@ -1485,8 +1522,13 @@ void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, 
 
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
-                     double* partials, size_t* n_part, hipStream_t s, int by, size_t cap) {
-  const ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
+                     double* partials, size_t* n_part, hipStream_t s, int by, size_t cap,
+                     bool last_colour_done) {
+  ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
+  // the norm needs every node's residual in this launch
+  if (last_colour_done && partials)
+    throw Error{MCW_HIP_ERROR, "internal error: a residual norm needs every column's residual"};
+  J.skip11 = last_colour_done ? 1 : 0;
   if (partials) need_partials((size_t)J.nblocks, cap);
   const bool h16 = sizeof(T) == 4 && st.h16;
   if (partials && h16)
@@ -1793,7 +1835,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 
 #define MCW_INST(T)                                                                             \
   template void launch_smooth_sweep<T>(const Dims&, const Faces&, StRef, const T*, T*,          \
-                                       hipStream_t, int, bool, T*);                             \
+                                       hipStream_t, int, bool, T*, T*);                         \
   template void launch_cg_beta<T>(const T*, const T*, const T*, size_t, double*, size_t,       \
                                   double*, hipStream_t);                                        \
   template void launch_add<T>(T*, const T*, size_t, hipStream_t);                              \
@@ -1803,7 +1845,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_neg_apply_dot<T>(const Dims&, const Faces&, StRef, const T*, T*,         \
                                         double*, size_t, size_t*, hipStream_t, int);            \
   template void launch_residual<T>(const Dims&, const Faces&, StRef, const T*, const T*, T*,    \
-                                   double*, size_t*, hipStream_t, int, size_t);                 \
+                                   double*, size_t*, hipStream_t, int, size_t, bool);           \
   template void launch_restrict<T>(const Dims&, const Dims&, const Faces&, const DirMapDev&,    \
                                    const DirMapDev&, const DirMapDev&, const T*, T*,            \
                                    hipStream_t);                                                \

@@ -336,9 +336,13 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
     return;
   }
   const StRef st = stencil_of<T>(L);
-  for (int s = 0; s < h.opt.nu_pre; ++s)
-    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L));
-  launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res);
+  // the last pre-smoothing sweep leaves the residual of its last colour behind
+  const int nu = h.opt.nu_pre;
+  for (int s = 0; s < nu; ++s)
+    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L),
+                           s == nu - 1 ? L.r.as<T>() : nullptr);
+  launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res, 0,
+                     nu > 0);
   Level& C = h.levels[l + 1];
   launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
   launch_fill<T>(C.x.as<T>(), C.d.N(), T(0), h.stream);
@@ -1288,15 +1292,18 @@ class Batch {
     depth_ = 0;
     for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
     gs_.assign(depth_, {});
+    gs3r_.assign(depth_, {});
     by_gs_.assign(depth_, 4);
     by_res_.assign(depth_, 4);
     res_.assign(depth_, {});
+    resv_.assign(depth_, {});
+    const bool r_last = hs_[0]->opt.nu_pre > 0;
     restr_.assign(depth_, {});
     fillx_.assign(depth_, {});
     prol_.assign(depth_, {});
     coarse_.assign(depth_, {});
     for (int d = 0; d < depth_; ++d) {
-      std::vector<ColJob> gsj[4], rj;
+      std::vector<ColJob> gsj[4], rj, g3r, rvj;
       std::vector<XferJob> rsj, pj;
       std::vector<VecJob> fj;
       std::vector<CoarseJob> cj;
@@ -1329,9 +1336,16 @@ class Batch {
           if (J.nblocks > 0) {
             gsj[c].push_back(J);
             gsm[c].push_back(i);
+            if (c == 3) {
+              // the last colour of the last pre-smoothing sweep writes its residual
+              g3r.push_back(J);
+              g3r.back().rlast = r_last ? V.r.p : nullptr;
+            }
           }
         }
         rj.push_back(col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
+        rvj.push_back(rj.back());
+        rvj.back().skip11 = r_last ? 1 : 0;
         rm.push_back(i);
         rsj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, V.r.p, C.f.p, true));
         rsm.push_back(i);
@@ -1341,7 +1355,9 @@ class Batch {
         fm.push_back(i);
       }
       for (int c = 0; c < 4; ++c) gs_[d][c] = add_split(gsj[c], gsm[c]);
+      gs3r_[d] = add_split(g3r, gsm[3]);
       res_[d] = add_split(rj, rm);
+      resv_[d] = add_split(rvj, rm);
       restr_[d] = add(rsj, rsm);
       prol_[d] = add(pj, pm);
       fillx_[d] = add(fj, fm);
@@ -1772,9 +1788,12 @@ class Batch {
     launch_coarse_batched<float>(fix(coarse_[d]), std::max(max_coarse_, 1), s_);
     if (res_[d].njobs() == 0) return;
     for (int s = 0; s < nu_pre; ++s)
-      for (int c = 0; c < 4; ++c)
-        for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(gs_[d][c].w[f]), s_, by_gs_[d], false, f == 1);
-    for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[d].w[f]), s_, by_res_[d], f == 1);
+      for (int c = 0; c < 4; ++c) {
+        const ByFormat& g = (c == 3 && s == nu_pre - 1) ? gs3r_[d] : gs_[d][c];
+        for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(g.w[f]), s_, by_gs_[d], false, f == 1);
+      }
+    // with pre-smoothing, the last colour's residual is already in place
+    for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(resv_[d].w[f]), s_, by_res_[d], f == 1);
     launch_restrict_batched<float>(fix(restr_[d]), s_);
     launch_fill_batched<float>(fix(fillx_[d]), s_);
     if (d + 1 < depth_) vcycle_levels(d + 1);
@@ -1895,8 +1914,10 @@ class Batch {
   size_t cg_slot_ = 0, cgtab_off_ = 0;
   int depth_ = 0, max_coarse_ = 0;
   std::vector<std::array<ByFormat, 4>> gs_;
+  std::vector<ByFormat> gs3r_;  // colour (1,1) writing r: the last pre-smoothing pass
   std::vector<int> by_gs_, by_res_;
-  std::vector<ByFormat> res_;
+  std::vector<ByFormat> res_;   // the full residual (kernel timing)
+  std::vector<ByFormat> resv_;  // the V-cycle's residual after pre-smoothing
   std::vector<WorkList> restr_, fillx_, prol_, coarse_;
   WorkList zf_{}, rhs_{}, res64_{}, div_{}, rec_{}, sc_{}, f0_{}, up_{};
   std::vector<VecJob> zf_jobs_, sc_jobs_, f0_jobs_, up_jobs_;

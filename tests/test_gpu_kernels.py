@@ -171,6 +171,26 @@ def test_vcycle_matches_oracle_vcycle(name):
     assert gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref) < 1e-10
 
 
+@pytest.mark.parametrize("nu", [(0, 2), (1, 1), (3, 2)])
+@pytest.mark.parametrize("smoother", ["point", "line"])
+@pytest.mark.parametrize("name", ["ragged", "tiles"])
+def test_vcycle_with_other_smoothing_counts(name, smoother, nu):
+    """The last colour pass of the last pre-smoothing sweep writes its columns'
+    residual and the residual kernel skips them; with no pre-smoothing the
+    residual kernel computes every column.  Each count and smoother against
+    the oracle's V-cycle (Sec. 3) of the same counts."""
+    g, _ = _grid(name, precision="fp64", coarse_direct_max=60, smoother=smoother,
+                 nu_pre=nu[0], nu_post=nu[1])
+    levels = gc.hierarchy(name, coarse_max=60)
+    M = mg.Multigrid(levels, nu_pre=nu[0], nu_post=nu[1], smoother=smoother)
+    L = levels[0]
+    x, f, _ = _level_vectors(gc.problem(name), L, 17)
+    xg = _dev(x)
+    g.vcycle(xg, _dev(f))
+    ref = M.vcycle(x.ravel()[L.free], f.ravel()[L.free])
+    assert gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref) < 1e-10
+
+
 def test_inverted_element_is_rejected():
     from paper_2101_08453_amd import mcwind
     p = gc.make("box")
