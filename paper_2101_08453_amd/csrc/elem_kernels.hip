@@ -624,13 +624,18 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by,
 
 // TFM: 0 general grid, 1 terrain-following grid, 2 read from *A.tf_flag (0 =
 // terrain-following), for a caller that only knows it on the device.
+// Tiles are taken in x-fastest order, each XCD a contiguous range of them:
+// a tile's node rows share their first and last cache lines with the tiles
+// beside it in x, which then run on the same XCD and find them in its L2.
 template <int MODE, int TFM>
 __global__ __launch_bounds__(256) void elem_tile_kernel(TileJob A) {
   __shared__ double smem[TFM == 2 ? tile_lds_max(MODE) : tile_lds_doubles(MODE, TFM == 1)];
+  const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = b % gridDim.x, by = b / gridDim.x;
   if (TFM == 1 || (TFM == 2 && *A.tf_flag == 0))
-    elem_tile_body<MODE, true>(A, blockIdx.x, blockIdx.y, smem);
+    elem_tile_body<MODE, true>(A, bx, by, smem);
   else
-    elem_tile_body<MODE, false>(A, blockIdx.x, blockIdx.y, smem);
+    elem_tile_body<MODE, false>(A, bx, by, smem);
 }
 
 template <int MODE>

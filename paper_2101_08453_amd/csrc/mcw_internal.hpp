@@ -103,6 +103,13 @@ __device__ __forceinline__ void block_sum_to(double v, double* s_red, double* ou
 // 1 KB block, with a single address per lane and immediate offsets.
 constexpr int SW = 28;
 
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so that neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, rem = n & 7, x = b & 7, s = b >> 3;
+  return x * q + min(x, rem) + s;
+}
+
 struct StLayout {
   int NY = 0, NXeP = 0, rowlen = 0;
   size_t nodes = 0;  // padded node count

@@ -119,13 +119,6 @@ __device__ __forceinline__ T scaled(T v, float s) {
   else return v * (T)s;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so that neighbouring tiles share an L2.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-  const int q = n >> 3, rem = n & 7, x = b & 7, s = b >> 3;
-  return x * q + min(x, rem) + s;
-}
-
 // Job owning global work item g of a batched launch (prefix has njobs+1 entries).
 __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int g) {
   int lo = 0, hi = njobs - 1;
