@@ -14,7 +14,7 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from oracle import multigrid as mg
+from oracle import fem, multigrid as mg
 from tests import gpu_cases as gc
 
 pytestmark = pytest.mark.gpu
@@ -134,3 +134,74 @@ def test_vcycle_matches_the_oracle_on_the_rounded_operators(name, fmt):
     err = gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref)
     print(f"  rel err {err:.1e}", flush=True)
     assert err < TOL
+
+
+# ---------------------------------------------------------------- full size
+
+def _window_sweep(p, x, f, ic, jc):
+    """The oracle's forward sweep and residual on a window around column
+    (ic, jc), from the inputs alone.  A column of colour c depends on the
+    sweep's new values of neighbour columns of earlier colours, which depend
+    on theirs, and so on: at most three rings out.  The 3x3 block around the
+    centre therefore needs exact rows up to four columns out, i.e. elements
+    up to five out.  The window starts at an even i and j, so that its local
+    colours are the global ones; rows at its inner edges are incomplete but
+    lie outside that reach.  Returns the block's (i, j) ranges, the swept x
+    and f - K x there, and a scale for each."""
+    nx, ny, nz = p.dims
+    i0, j0 = max(ic - 5, 0) & ~1, max(jc - 5, 0) & ~1
+    i1, j1 = min(ic + 6, nx + 1), min(jc + 6, ny + 1)
+    X, Y, Z = (np.ascontiguousarray(A[:, j0:j1, i0:i1]) for A in (p.X, p.Y, p.Z))
+    K = fem.assemble_stiffness(X, Y, Z, p.a)
+    mask = fem.free_mask(nx, ny, nz, p.gamma)[:, j0:j1, i0:i1].ravel()
+    xw = x[:, j0:j1, i0:i1].astype(np.float64).ravel()
+    fw = f[:, j0:j1, i0:i1].astype(np.float64).ravel()
+    dims = (i1 - i0 - 1, j1 - j0 - 1, nz)
+    xs = mg.gs_sweep_full(K, mask, dims, xw, fw)
+    r = np.where(mask, fw - K @ xw, 0.0)
+    scale = np.abs(fw) + abs(K) @ np.abs(xw)
+    sh = (nz + 1, j1 - j0, i1 - i0)
+    bi = slice(max(ic - 1, 0) - i0, min(ic + 2, nx + 1) - i0)
+    bj = slice(max(jc - 1, 0) - j0, min(jc + 2, ny + 1) - j0)
+    blk = (slice(None), bj, bi)
+    return ((bj.start + j0, bj.stop + j0), (bi.start + i0, bi.stop + i0),
+            xs.reshape(sh)[blk], r.reshape(sh)[blk], scale.reshape(sh)[blk])
+
+
+@pytest.mark.parametrize("fmt,tol", [("fp32", 3e-5), ("fp16", 5e-3)])
+def test_3000x3000x15_colour_pass_and_residual_sampled(fmt, tol):
+    """The benchmark's grid and launch shapes (3000x3000x15, a = (1,1,10), the
+    fused two-colour passes of the fine level, its residual kernel): one
+    forward sweep and one residual of seeded random x and f, against the
+    oracle's sweep and f - K x on windows around 12 columns (corners, edges,
+    interior), with K assembled by the oracle from the geometry in FP64.  The
+    bound covers the FP32 (or FP16) rounding of the stencil and the FP32
+    arithmetic; a misplaced coefficient moves results by O(1)."""
+    from paper_2101_08453_amd import inputs, mcwind
+    p = inputs.c3()
+    nx, ny, nz = p.dims
+    rng = np.random.default_rng(71)
+    m = fem.free_mask(nx, ny, nz, p.gamma)
+    x = rng.standard_normal(m.shape, dtype=np.float32) * m
+    f = rng.standard_normal(m.shape, dtype=np.float32) * m
+    print(f"[case] 3000x3000x15 colour pass and residual, {fmt} stencils", flush=True)
+    dev = torch.device("cuda")
+    g = mcwind.Grid(*(torch.from_numpy(A).to(dev) for A in (p.X, p.Y, p.Z)), p.a,
+                    precision="fp32_refine", **FORMATS[fmt])
+    xd, fd = torch.from_numpy(x).to(dev), torch.from_numpy(f).to(dev)
+    r_gpu = g.residual(0, xd, fd)
+    g.smooth(0, xd, fd, sweeps=1)
+    centres = [(1, 1), (2999, 1), (1, 2999), (2999, 2999), (1500, 1501), (733, 2048)]
+    centres += [tuple(int(v) for v in rng.integers(6, 2994, 2)) for _ in range(6)]
+    worst_x = worst_r = 0.0
+    for ic, jc in centres:
+        (ja, jb), (ia, ib), xs, r, scale = _window_sweep(p, x, f, ic, jc)
+        xg = xd[:, ja:jb, ia:ib].cpu().numpy().astype(np.float64)
+        rg = r_gpu[:, ja:jb, ia:ib].cpu().numpy().astype(np.float64)
+        ex = np.abs(xg - xs).max() / max(np.abs(xs).max(), 1e-30)
+        er = (np.abs(rg - r) / np.maximum(scale, 1e-30)).max()
+        worst_x, worst_r = max(worst_x, ex), max(worst_r, er)
+        assert ex <= tol, f"sweep at column ({ic}, {jc}): {ex:.2e}"
+        assert er <= tol, f"residual at column ({ic}, {jc}): {er:.2e}"
+    print(f"  worst: sweep {worst_x:.1e}, residual {worst_r:.1e}", flush=True)
+    g.close()
