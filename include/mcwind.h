@@ -383,9 +383,15 @@ mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps
 /* Run `reps` launches of one batched phase over the finest level of m handles
  * (as mcw_solve_batch runs it; all members take part, on their own level
  * buffers and current contents) and wait: kernel 0 = one Gauss-Seidel sweep
- * (four batched colour passes), 1 = the residual.  FP32_REFINE point-smoother
- * members with equal krylov and smoothing counts.  For timing and profiling. */
-mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps);
+ * (two batched two-colour launches where the largest member's fine level uses
+ * the fused pass, else four batched colour passes), 1 = the residual.
+ * FP32_REFINE point-smoother members with equal krylov and smoothing counts.
+ * ms_per_rep (host, may be NULL) receives the device time per repetition,
+ * taken with HIP events on the batch's stream around the launches only;
+ * launches_per_rep (host, may be NULL) the launches of one repetition per
+ * stencil format.  For timing and profiling. */
+mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps,
+                                float* ms_per_rep, int32_t* launches_per_rep);
 
 /* Tile shape used on level l by the Gauss-Seidel colour pass and by the
  * residual (host int32 outputs): rows of 64 columns per block, and for the

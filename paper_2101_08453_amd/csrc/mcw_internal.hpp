@@ -251,6 +251,11 @@ struct ColJob {  // smoother colour pass, residual
   int skip11;            // residual: colour (1,1) columns already hold r (written by rlast)
 };
 
+struct FusedJob {  // two colour passes of the same rows, one block per row (batched)
+  ColJob J0, J1;
+  int nblocks;  // rows: J0.ncy
+};
+
 struct XferJob {  // restriction rc = P^T r (src = r, dst = rc); prolongation x += P e (src = e, dst = x)
   const void* src;
   void* dst;
@@ -542,6 +547,8 @@ template <class T> void launch_neg_apply_dot_batched(const WorkList& W, hipStrea
 void launch_cg_coeff_batched(const CgJob* jobs, int n, int mode, const int* active, hipStream_t s);
 void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStream_t s);
 template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16);
+// FusedJob work items: colour J0 then J1 of one row per block (as gs_fused_kernel)
+template <class T> void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16);
 template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s);

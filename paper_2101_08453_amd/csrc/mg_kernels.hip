@@ -399,6 +399,25 @@ __global__ __launch_bounds__(256) void gs_pass_batched_rev(WorkList W) {
   MCW_BATCHED_LOOP(ColJob, (gs_pass_rev<T, SF>))
 }
 
+// Batched two-colour pass: work item b of a job is row 2b + cj, run as
+// gs_fused_kernel runs a row (colour J0, block barrier, colour J1), with
+// blocks of 256 threads looping over the row's columns.  Every thread of a
+// block walks the same work items, so the barrier is reached uniformly.
+template <class T, bool REV, int SF>
+__device__ __forceinline__ void gs_fused_item(const FusedJob& F, int b) {
+  const int j = 2 * b + F.J0.cj;
+  for (int ii = threadIdx.x; ii < F.J0.ncx; ii += blockDim.x)
+    gs_column<T, REV, SF>(F.J0, 2 * ii + F.J0.ci, j);
+  __syncthreads();
+  for (int ii = threadIdx.x; ii < F.J1.ncx; ii += blockDim.x)
+    gs_column<T, REV, SF>(F.J1, 2 * ii + F.J1.ci, j);
+}
+
+template <class T, bool REV, int SF>
+__global__ __launch_bounds__(256) void gs_fused_batched(WorkList W) {
+  MCW_BATCHED_LOOP(FusedJob, (gs_fused_item<T, REV, SF>))
+}
+
 // ---------------------------------------------------------------- residual
 
 // r = f - K x at free nodes (f null: r = -K x), 0 at fixed nodes; returns this
@@ -1716,6 +1735,27 @@ void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, b
   launch_gs_batched_f<T, 0>(W, s, by, reverse);
 }
 
+template <class T, int SF>
+void launch_gs_fused_batched_f(const WorkList& W, hipStream_t s, bool reverse) {
+  if (reverse)
+    gs_fused_batched<T, true, SF><<<batched_grid(W.total), 256, 0, s>>>(W);
+  else
+    gs_fused_batched<T, false, SF><<<batched_grid(W.total), 256, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16) {
+  if (W.total <= 0) return;
+  if constexpr (sizeof(T) == 4) {
+    if (h16) {
+      launch_gs_fused_batched_f<T, 1>(W, s, reverse);
+      return;
+    }
+  }
+  launch_gs_fused_batched_f<T, 0>(W, s, reverse);
+}
+
 template <class T>
 void launch_dot2_batched(const WorkList& W, hipStream_t s) {
   if (W.total <= 0) return;
@@ -1849,6 +1889,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
                                        hipStream_t);                                            \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
   template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool, bool);            \
+  template void launch_gs_fused_batched<T>(const WorkList&, hipStream_t, bool, bool);           \
   template void launch_residual_batched<T>(const WorkList&, hipStream_t, int, bool);            \
   template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
   template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \

@@ -1293,6 +1293,10 @@ class Batch {
     for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
     gs_.assign(depth_, {});
     gs3r_.assign(depth_, {});
+    gsf_.assign(depth_, {});
+    gsfr_.assign(depth_, {});
+    gsf3r_.assign(depth_, {});
+    fused_.assign(depth_, 0);
     by_gs_.assign(depth_, 4);
     by_res_.assign(depth_, 4);
     res_.assign(depth_, {});
@@ -1304,6 +1308,8 @@ class Batch {
     coarse_.assign(depth_, {});
     for (int d = 0; d < depth_; ++d) {
       std::vector<ColJob> gsj[4], rj, g3r, rvj;
+      std::vector<FusedJob> fj2[2], fr2[2], f3r;
+      std::vector<int> fm2[2], frm2[2];
       std::vector<XferJob> rsj, pj;
       std::vector<VecJob> fj;
       std::vector<CoarseJob> cj;
@@ -1314,8 +1320,10 @@ class Batch {
         mcw_handle& h = *hs_[i];
         if (d + 1 < (int)h.levels.size() && h.levels[d].d.N() > big) {
           big = h.levels[d].d.N();
-          by_gs_[d] = std::max(1, h.levels[d].by_gs);  // batched passes are per colour
+          by_gs_[d] = std::max(1, h.levels[d].by_gs);  // per-colour passes: tiles of rows
           by_res_[d] = h.levels[d].by_res;
+          // where the largest member's tuned pass is the fused one, so is the batch's
+          fused_[d] = h.levels[d].by_gs == 0 ? 1 : 0;
         }
       }
       for (int i = 0; i < m_; ++i) {
@@ -1343,6 +1351,30 @@ class Batch {
             }
           }
         }
+        // the two-colour passes: (0,0),(1,0) on even rows, (0,1),(1,1) on odd
+        // rows; reversed (1,1),(0,1) then (1,0),(0,0)
+        for (int pr = 0; pr < 2; ++pr) {
+          FusedJob F{};
+          F.J0 = col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, nullptr, 2 * pr, 1);
+          F.J1 = col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, nullptr, 2 * pr + 1, 1);
+          F.nblocks = std::max(0, F.J0.ncy);
+          if (F.nblocks > 0) {
+            fj2[pr].push_back(F);
+            fm2[pr].push_back(i);
+            if (pr == 1) {
+              f3r.push_back(F);
+              f3r.back().J1.rlast = r_last ? V.r.p : nullptr;
+            }
+          }
+          FusedJob R{};
+          R.J0 = col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, nullptr, 3 - 2 * pr, 1);
+          R.J1 = col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, nullptr, 2 - 2 * pr, 1);
+          R.nblocks = std::max(0, R.J0.ncy);
+          if (R.nblocks > 0) {
+            fr2[pr].push_back(R);
+            frm2[pr].push_back(i);
+          }
+        }
         rj.push_back(col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
         rvj.push_back(rj.back());
         rvj.back().skip11 = r_last ? 1 : 0;
@@ -1356,6 +1388,11 @@ class Batch {
       }
       for (int c = 0; c < 4; ++c) gs_[d][c] = add_split(gsj[c], gsm[c]);
       gs3r_[d] = add_split(g3r, gsm[3]);
+      for (int pr = 0; pr < 2; ++pr) {
+        gsf_[d][pr] = add_split(fj2[pr], fm2[pr]);
+        if (krylov_) gsfr_[d][pr] = add_split(fr2[pr], frm2[pr]);
+      }
+      gsf3r_[d] = add_split(f3r, fm2[1]);
       res_[d] = add_split(rj, rm);
       resv_[d] = add_split(rvj, rm);
       restr_[d] = add(rsj, rsm);
@@ -1674,21 +1711,47 @@ class Batch {
 
   // For timing: `reps` launches of one batched phase over every member's finest
   // level on the members' own buffers (their current contents), all members
-  // taking part.  kernel 0: one Gauss-Seidel sweep (four batched colour
-  // passes), 1: the residual.
-  void run_fine(int kernel, int reps) {
+  // taking part.  kernel 0: one Gauss-Seidel sweep (two fused two-colour
+  // launches, or four colour passes), 1: the residual.  Returns the device ms
+  // per repetition (HIP events on the batch's stream around the launches) and
+  // the launches per repetition of each stencil format present.
+  std::pair<float, int> run_fine(int kernel, int reps) {
     set_active(std::vector<int>(m_, 1));
     upload();
-    for (int r = 0; r < reps; ++r) {
-      if (kernel == 0) {
-        for (int c = 0; c < 4; ++c)
-          for (int f = 0; f < 2; ++f)
-            launch_gs_batched<float>(fix(gs_[0][c].w[f]), s_, by_gs_[0], false, f == 1);
-      } else {
-        for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[0].w[f]), s_, by_res_[0], f == 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MCW_HIP(hipEventCreate(&e0));
+    MCW_HIP(hipEventCreate(&e1));
+    int launches = 0;
+    try {
+      MCW_HIP(hipEventRecord(e0, s_));
+      for (int r = 0; r < reps; ++r) {
+        if (kernel == 0 && fused_[0]) {
+          for (int pr = 0; pr < 2; ++pr)
+            for (int f = 0; f < 2; ++f)
+              launch_gs_fused_batched<float>(fix(gsf_[0][pr].w[f]), s_, false, f == 1);
+          launches = 2;
+        } else if (kernel == 0) {
+          for (int c = 0; c < 4; ++c)
+            for (int f = 0; f < 2; ++f)
+              launch_gs_batched<float>(fix(gs_[0][c].w[f]), s_, by_gs_[0], false, f == 1);
+          launches = 4;
+        } else {
+          for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[0].w[f]), s_, by_res_[0], f == 1);
+          launches = 1;
+        }
       }
+      MCW_HIP(hipEventRecord(e1, s_));
+      MCW_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      MCW_HIP(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return {ms / reps, launches};
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
     }
-    MCW_HIP(hipStreamSynchronize(s_));
   }
 
  private:
@@ -1720,11 +1783,14 @@ class Batch {
     WorkList w[2]{};
     int njobs() const { return w[0].njobs + w[1].njobs; }
   };
-  ByFormat add_split(const std::vector<ColJob>& jobs, const std::vector<int>& members) {
-    std::vector<ColJob> js[2];
+  static int format_of(const ColJob& J) { return J.h16 ? 1 : 0; }
+  static int format_of(const FusedJob& F) { return F.J0.h16 ? 1 : 0; }
+  template <class J>
+  ByFormat add_split(const std::vector<J>& jobs, const std::vector<int>& members) {
+    std::vector<J> js[2];
     std::vector<int> ms[2];
     for (size_t k = 0; k < jobs.size(); ++k) {
-      const int f = jobs[k].h16 ? 1 : 0;
+      const int f = format_of(jobs[k]);
       js[f].push_back(jobs[k]);
       ms[f].push_back(members[k]);
     }
@@ -1734,6 +1800,7 @@ class Batch {
   }
 
   static int nblocks_of(const ColJob& J) { return J.nblocks; }
+  static int nblocks_of(const FusedJob& F) { return F.nblocks; }
   static int nblocks_of(const XferJob& X) { return X.nblocks; }
   static int nblocks_of(const CoarseJob& C) { return C.nblocks; }
   static int nblocks_of(const VecJob& V) { return V.nblocks; }
@@ -1787,11 +1854,19 @@ class Batch {
     const int nu_pre = hs_[0]->opt.nu_pre, nu_post = hs_[0]->opt.nu_post;
     launch_coarse_batched<float>(fix(coarse_[d]), std::max(max_coarse_, 1), s_);
     if (res_[d].njobs() == 0) return;
-    for (int s = 0; s < nu_pre; ++s)
+    for (int s = 0; s < nu_pre; ++s) {
+      if (fused_[d]) {
+        for (int pr = 0; pr < 2; ++pr) {
+          const ByFormat& g = (pr == 1 && s == nu_pre - 1) ? gsf3r_[d] : gsf_[d][pr];
+          for (int f = 0; f < 2; ++f) launch_gs_fused_batched<float>(fix(g.w[f]), s_, false, f == 1);
+        }
+        continue;
+      }
       for (int c = 0; c < 4; ++c) {
         const ByFormat& g = (c == 3 && s == nu_pre - 1) ? gs3r_[d] : gs_[d][c];
         for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(g.w[f]), s_, by_gs_[d], false, f == 1);
       }
+    }
     // with pre-smoothing, the last colour's residual is already in place
     for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(resv_[d].w[f]), s_, by_res_[d], f == 1);
     launch_restrict_batched<float>(fix(restr_[d]), s_);
@@ -1799,11 +1874,19 @@ class Batch {
     if (d + 1 < depth_) vcycle_levels(d + 1);
     launch_prolong_batched<float>(fix(prol_[d]), s_);
     // with CG the post-smoother is the reverse sweep, which keeps the cycle symmetric
-    for (int s = 0; s < nu_post; ++s)
+    for (int s = 0; s < nu_post; ++s) {
+      if (fused_[d]) {
+        for (int pr = 0; pr < 2; ++pr) {
+          const ByFormat& g = krylov_ ? gsfr_[d][pr] : gsf_[d][pr];
+          for (int f = 0; f < 2; ++f) launch_gs_fused_batched<float>(fix(g.w[f]), s_, krylov_, f == 1);
+        }
+        continue;
+      }
       for (int cc = 0; cc < 4; ++cc) {
         const int c = krylov_ ? 3 - cc : cc;
         for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(gs_[d][c].w[f]), s_, by_gs_[d], krylov_, f == 1);
       }
+    }
   }
 
   // One batched CG step for the members whose flag is on (the single-handle
@@ -1915,6 +1998,11 @@ class Batch {
   int depth_ = 0, max_coarse_ = 0;
   std::vector<std::array<ByFormat, 4>> gs_;
   std::vector<ByFormat> gs3r_;  // colour (1,1) writing r: the last pre-smoothing pass
+  // two-colour passes (forward pairs, reversed pairs, the last pre-smoothing
+  // pair writing r), used at the depths where fused_ is set
+  std::vector<std::array<ByFormat, 2>> gsf_, gsfr_;
+  std::vector<ByFormat> gsf3r_;
+  std::vector<char> fused_;
   std::vector<int> by_gs_, by_res_;
   std::vector<ByFormat> res_;   // the full residual (kernel timing)
   std::vector<ByFormat> resv_;  // the V-cycle's residual after pre-smoothing
@@ -1945,7 +2033,8 @@ void check_batch_handles(int m, mcw_handle* const* hs) {
   }
 }
 
-mcw_status run_kernel_batch_impl(int m, mcw_handle* const* hs, int kernel, int reps) {
+mcw_status run_kernel_batch_impl(int m, mcw_handle* const* hs, int kernel, int reps,
+                                 float* ms_per_rep, int32_t* launches_per_rep) {
   if (m < 1 || !hs) Fail::arg("need at least one member");
   if (kernel < 0 || kernel > 1 || reps < 1 || reps > 10000) Fail::arg("bad kernel or reps");
   check_batch_handles(m, hs);
@@ -1956,7 +2045,9 @@ mcw_status run_kernel_batch_impl(int m, mcw_handle* const* hs, int kernel, int r
   for (int i = 1; i < m; ++i) MCW_HIP(hipStreamSynchronize(hs[i]->stream));
   Batch b(std::vector<mcw_handle*>(hs, hs + m));
   b.build();
-  b.run_fine(kernel, reps);
+  const std::pair<float, int> t = b.run_fine(kernel, reps);
+  if (ms_per_rep) *ms_per_rep = t.first;
+  if (launches_per_rep) *launches_per_rep = t.second;
   return MCW_OK;
 }
 
@@ -2380,8 +2471,11 @@ mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f) {
   });
 }
 
-mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps) {
-  return guarded(nullptr, [&] { return run_kernel_batch_impl(m, hs, kernel, reps); });
+mcw_status mcw_run_kernel_batch(int32_t m, mcw_handle* const* hs, int32_t kernel, int32_t reps,
+                                float* ms_per_rep, int32_t* launches_per_rep) {
+  return guarded(nullptr, [&] {
+    return run_kernel_batch_impl(m, hs, kernel, reps, ms_per_rep, launches_per_rep);
+  });
 }
 
 mcw_status mcw_run_kernel(mcw_handle* h, int32_t l, int32_t kernel, int32_t reps) {

@@ -123,7 +123,8 @@ SIGNATURES = {
     "mcw_coarse_solve": (I32, [H, P, P]),
     "mcw_vcycle": (I32, [H, P, P]),
     "mcw_run_kernel": (I32, [H, I32, I32, I32]),
-    "mcw_run_kernel_batch": (I32, [I32, ctypes.POINTER(H), I32, I32]),
+    "mcw_run_kernel_batch": (I32, [I32, ctypes.POINTER(H), I32, I32, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(I32)]),
     "mcw_interp_wind": (I32, [H, ctypes.POINTER(CoarseWind), P]),
     "mcw_surface_wind": (I32, [H, P, ctypes.c_double, ctypes.c_double, P]),
     "mcw_tile_shape": (I32, [H, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
@@ -469,12 +470,16 @@ def divergence_noalloc(X, Y, Z, a, u0, lam, gamma=GAMMA_BOTTOM, want_rel=True):
 
 def run_kernel_batch(grids, kernel, reps=1):
     """Launch one batched phase over the finest level of every grid `reps` times
-    (mcw_run_kernel_batch; "smooth" = one sweep, "residual"), for timing."""
+    (mcw_run_kernel_batch; "smooth" = one sweep, "residual"), for timing.
+    Returns (device ms per repetition, launches per repetition and format)."""
     m = len(grids)
     hs = (H * m)(*[g._h.value for g in grids])
-    st = lib().mcw_run_kernel_batch(m, hs, {"smooth": 0, "residual": 1}[kernel], int(reps))
+    ms, launches = ctypes.c_float(0.0), I32(0)
+    st = lib().mcw_run_kernel_batch(m, hs, {"smooth": 0, "residual": 1}[kernel], int(reps),
+                                    ctypes.byref(ms), ctypes.byref(launches))
     if st != MCW_OK:
         raise MCWError(st, lib().mcw_last_error(None).decode())
+    return ms.value, launches.value
 
 
 def grid_from_problem(prob, device="cuda", **kw):

@@ -192,3 +192,33 @@ def test_batched_kernel_timing_entry_point_leaves_solves_unchanged():
         assert torch.equal(a, b)
     with pytest.raises(mcwind.MCWError):
         mcwind.run_kernel_batch(grids, "smooth", 0)
+
+
+@pytest.mark.parametrize("shape", [0, 2])
+def test_batched_colour_passes_match_single_cg_bit_for_bit(tmp_path, monkeypatch, shape):
+    """Batched CG takes each member's own steps with the single kernels'
+    arithmetic, whether the batch's finest depth runs the two-colour pass (one
+    block per row, tile shape 0) or the one-colour tiles (2 rows of 64
+    columns): every member's multiplier equals its single CG solve bit for bit.
+    The fine levels' shapes are fixed through the tuning cache."""
+    mcwind = _mcw()
+    probs = [inputs.hills_problem(160, 120, 8, 3, 411, a=(1.0, 1.0, 3.0)),
+             inputs.hills_problem(100, 90, 8, 2, 412, a=(1.0, 1.0, 1.0))]
+    entries = []
+    for p in probs:
+        shp = f"{p.dims[0] + 1}x{p.dims[1] + 1}x{p.dims[2] + 1}"
+        entries += [f'  "gfx950|gsf|{shp}|f32": {shape}', f'  "gfx950|res|{shp}|f32": 4']
+    cache = tmp_path / "tune.json"
+    cache.write_text("{\n" + ",\n".join(entries) + "\n}\n")
+    monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
+    print(f"[case] batched CG, fine tile shape {shape}", flush=True)
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p, krylov=True, rtol=1e-10)
+                                         for p in probs])]
+    for g in grids:
+        assert g.tile_rows(0)[0] == shape
+    singles = [g.solve(u0, want_u=False)[0].clone() for g, u0 in zip(grids, u0s)]
+    lams, _, infos, st = mcwind.solve_batch(grids, u0s, want_u=False)
+    assert st == "MCW_OK"
+    for lam, ref, info in zip(lams, singles, infos):
+        assert info["rel_residual"] <= 1e-10
+        assert torch.equal(lam, ref)
