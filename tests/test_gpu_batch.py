@@ -185,8 +185,10 @@ def test_batched_kernel_timing_entry_point_leaves_solves_unchanged():
     print("[case] batched kernel timing entry point", flush=True)
     grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p) for p in probs])]
     lams, _, _, _ = mcwind.solve_batch(grids, u0s, want_u=False)
-    mcwind.run_kernel_batch(grids, "smooth", 3)
-    mcwind.run_kernel_batch(grids, "residual", 2)
+    ms, launches = mcwind.run_kernel_batch(grids, "smooth", 3)
+    assert ms > 0.0 and launches in (2, 4)  # two-colour launches, or one colour per launch
+    ms, launches = mcwind.run_kernel_batch(grids, "residual", 2)
+    assert ms > 0.0 and launches == 1
     lams2, _, _, _ = mcwind.solve_batch(grids, u0s, want_u=False)
     for a, b in zip(lams, lams2):
         assert torch.equal(a, b)
