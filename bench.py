@@ -207,10 +207,25 @@ def cpu_baseline(p, du, gw=None, n_sample=240):
                        np.ascontiguousarray(p.Y[:, :m + 1, :m + 1]),
                        np.ascontiguousarray(p.Z[:, :m + 1, :m + 1]),
                        np.ascontiguousarray(p.u0[:, :, :m, :m] + du[:, :, :m, :m]), p.a)
+    def window(mw):
+        return inputs.Problem("window", np.ascontiguousarray(p.X[:, :mw + 1, :mw + 1]),
+                              np.ascontiguousarray(p.Y[:, :mw + 1, :mw + 1]),
+                              np.ascontiguousarray(p.Z[:, :mw + 1, :mw + 1]),
+                              np.ascontiguousarray(p.u0[:, :, :mw, :mw] + du[:, :, :mw, :mw]), p.a)
+
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         lam, u, info = osolve.solve(w, method="cg", rtol=1e-8)
         t = time.perf_counter() - t0
+        # the half-size window, for the growth of the CG iteration count
+        _, _, info_h = osolve.solve(window(m // 2), method="cg", rtol=1e-8)
+    # The whole grid, extrapolated: assembly and the time per CG iteration grow
+    # with the nodes, the iterations as measured between the two windows.
+    growth = np.log2(info["iterations"] / info_h["iterations"])
+    n_full = p.n_nodes
+    iters_full = info["iterations"] * (p.dims[0] / m) ** growth
+    t_full = n_full * (info["t_assemble"] / w.n_nodes
+                       + info["t_solve"] / info["iterations"] / w.n_nodes * iters_full)
     out = {
         "value": w.n_nodes / t / 1e6, "unit": "Mnodes/s", "cores": 1, "kind": "oracle",
         "host_cpus": os.cpu_count(),
@@ -218,6 +233,13 @@ def cpu_baseline(p, du, gw=None, n_sample=240):
                    f"cold Jacobi-PCG to rel. residual 1e-8 incl. assembly and recovery: "
                    f"{t:.1f} s, {info['iterations']} CG iterations, 1 thread of "
                    f"{os.cpu_count()} host CPUs"),
+        "extrapolated_full_grid": {
+            "s": float(round(t_full, 0)), "Mnodes/s": float(n_full / t_full / 1e6),
+            "cg_iterations": int(round(iters_full)),
+            "how": (f"extrapolated, not run: assembly and time per CG iteration per node from the "
+                    f"{m}^2 window, times {n_full} nodes; iterations {info['iterations']} x "
+                    f"({p.dims[0]}/{m})^{growth:.2f}, the exponent from the {m // 2}^2 window's "
+                    f"{info_h['iterations']} iterations")},
     }
     if gw is not None:
         out["gpu_lambda_vs_oracle"] = oracle_window_check(p, du, gw)
@@ -707,7 +729,9 @@ def main():
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         cpu = cpu_baseline(p, du, gw)
-        log(f"cpu baseline: {cpu['value']:.4f} Mnodes/s ({time.perf_counter() - t0:.1f} s)")
+        x = cpu["extrapolated_full_grid"]
+        log(f"cpu baseline: {cpu['value']:.4f} Mnodes/s ({time.perf_counter() - t0:.1f} s); "
+            f"whole grid extrapolated: {x['s'] / 3600:.1f} h, {x['cg_iterations']} CG iterations")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mnodes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
