@@ -1066,14 +1066,41 @@ __global__ __launch_bounds__(256) void relayout_kernel(const T* __restrict__ src
   }
 }
 
+// Only the fixed nodes are visited: the whole planes below kf and above kl,
+// then on each free plane the x = 0, x = NX-1, y = 0 and y = NY-1 lines that are
+// fixed (a corner may be written twice, with the same zero).
 __device__ __forceinline__ void zero_fixed_body(const VecJob& V, int b) {
   double* __restrict__ v = static_cast<double*>(V.p);
   const int NX = V.NX, NY = V.NY, NZ = V.NZ;
-  const size_t plane = (size_t)NX * NY, N = plane * NZ;
+  const size_t plane = (size_t)NX * NY;
   const int kf = V.fc.k_first(), kl = V.fc.k_last(NZ);
-  for (size_t n = (size_t)b * 256 + threadIdx.x; n < N; n += (size_t)V.nblocks * 256) {
-    const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / plane);
-    if (V.fc.x_fixed(i, NX) || V.fc.y_fixed(j, NY) || k < kf || k > kl) v[n] = 0.0;
+  const size_t below = (size_t)kf * plane;                                  // planes 0..kf-1
+  const size_t above = (size_t)(NZ - 1 - (kl >= kf - 1 ? kl : kf - 1)) * plane;  // planes kl+1..NZ-1
+  const size_t line = 2 * (size_t)NY + 2 * (size_t)NX;                      // face nodes of a plane
+  const size_t nfree = kl >= kf ? (size_t)(kl - kf + 1) : 0;
+  const size_t total = below + above + nfree * line;
+  const bool fx0 = V.fc.x_fixed(0, NX), fx1 = V.fc.x_fixed(NX - 1, NX);
+  const bool fy0 = V.fc.y_fixed(0, NY), fy1 = V.fc.y_fixed(NY - 1, NY);
+  for (size_t t = (size_t)b * 256 + threadIdx.x; t < total; t += (size_t)V.nblocks * 256) {
+    if (t < below) {
+      v[t] = 0.0;
+    } else if (t < below + above) {
+      v[(size_t)NZ * plane - above + (t - below)] = 0.0;
+    } else {
+      const size_t u = t - below - above;
+      const size_t k = (size_t)kf + u / line;
+      const size_t r = u % line;
+      double* pl = v + k * plane;
+      if (r < (size_t)NY) {
+        if (fx0) pl[r * NX] = 0.0;
+      } else if (r < 2 * (size_t)NY) {
+        if (fx1) pl[(r - NY) * NX + NX - 1] = 0.0;
+      } else if (r < 2 * (size_t)NY + NX) {
+        if (fy0) pl[r - 2 * (size_t)NY] = 0.0;
+      } else {
+        if (fy1) pl[(size_t)(NY - 1) * NX + (r - 2 * (size_t)NY - NX)] = 0.0;
+      }
+    }
   }
 }
 
@@ -1120,10 +1147,22 @@ __global__ __launch_bounds__(256) void axpy64_kernel(double alpha, const double*
 
 // Deterministic final sum of per-block partials: thread t adds entries
 // t, t+256, ... in order, then a fixed tree.
+// Each thread adds partials i, i + 256, i + 512, ... in that order; eight are
+// loaded before the first of them is added, so the loads overlap instead of
+// each waiting for the add before it (same order of additions, same result).
 __device__ __forceinline__ void sum_body(const SumJob& S, double* s) {
   for (int w = 0; w < S.width; ++w) {
+    const double* __restrict__ p = S.partials + (size_t)w * S.n_part;
     double a = 0.0;
-    for (size_t i = threadIdx.x; i < S.n_part; i += 256) a += S.partials[(size_t)w * S.n_part + i];
+    size_t i = threadIdx.x;
+    for (; i + 7 * 256 < S.n_part; i += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[i + (size_t)u * 256];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; i < S.n_part; i += 256) a += p[i];
     block_sum_to(a, s, &S.out[w]);
   }
 }

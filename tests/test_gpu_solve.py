@@ -109,6 +109,28 @@ def test_warm_start_from_solution_needs_no_cycles():
     assert info2["cycles"] == 0 and info2["rel_residual"] <= 1e-10
 
 
+@pytest.mark.parametrize("gamma", [1, 0, 0b000011, 0b111100, 0b011101])
+def test_warm_start_values_at_fixed_nodes_are_cleared(gamma):
+    """A warm start may hold anything at the fixed nodes (lambda = 0 outside
+    Gamma, Sec. 2): the solve zeroes them before it starts, so the result equals
+    the cold solve's at the same tolerance and is exactly zero there.  Gamma
+    is the bottom, no face, bottom and top, the four side faces, or the bottom
+    with three side faces."""
+    mcwind = _mcw()
+    p = inputs.hills_problem(23, 17, 5, 2, 31, a=(1.0, 1.0, 3.0))
+    p.gamma = gamma
+    print(f"[case] warm start with garbage at fixed nodes, gamma {gamma:06b}", flush=True)
+    g, u0 = mcwind.grid_from_problem(p, precision="fp64", rtol=1e-12)
+    lam_cold, _, _ = g.solve(u0, want_u=False)
+    rng = np.random.default_rng(gamma + 7)
+    warm = _dev(rng.standard_normal(lam_cold.shape))
+    lam, _, info = g.solve(u0, lam=warm, want_u=False)
+    assert info["rel_residual"] <= 1e-12
+    m = torch.from_numpy(fem.free_mask(*p.dims, gamma)).to("cuda")
+    assert float(lam[~m].abs().max()) == 0.0
+    assert float((lam - lam_cold).abs().max() / lam_cold.abs().max()) < 1e-9
+
+
 def test_zero_and_horizontal_wind_give_zero_multiplier():
     mcwind = _mcw()
     p = gc.make("box")
