@@ -1718,40 +1718,39 @@ class Batch {
   std::pair<float, int> run_fine(int kernel, int reps) {
     set_active(std::vector<int>(m_, 1));
     upload();
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    MCW_HIP(hipEventCreate(&e0));
-    MCW_HIP(hipEventCreate(&e1));
-    int launches = 0;
-    try {
-      MCW_HIP(hipEventRecord(e0, s_));
-      for (int r = 0; r < reps; ++r) {
-        if (kernel == 0 && fused_[0]) {
-          for (int pr = 0; pr < 2; ++pr)
-            for (int f = 0; f < 2; ++f)
-              launch_gs_fused_batched<float>(fix(gsf_[0][pr].w[f]), s_, false, f == 1);
-          launches = 2;
-        } else if (kernel == 0) {
-          for (int c = 0; c < 4; ++c)
-            for (int f = 0; f < 2; ++f)
-              launch_gs_batched<float>(fix(gs_[0][c].w[f]), s_, by_gs_[0], false, f == 1);
-          launches = 4;
-        } else {
-          for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[0].w[f]), s_, by_res_[0], f == 1);
-          launches = 1;
-        }
+    struct Events {  // destroyed on every way out
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
       }
-      MCW_HIP(hipEventRecord(e1, s_));
-      MCW_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      MCW_HIP(hipEventElapsedTime(&ms, e0, e1));
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return {ms / reps, launches};
-    } catch (...) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      throw;
+    } ev;
+    MCW_HIP(hipEventCreate(&ev.e[0]));
+    MCW_HIP(hipEventCreate(&ev.e[1]));
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
+    int launches = 0;
+    MCW_HIP(hipEventRecord(e0, s_));
+    for (int r = 0; r < reps; ++r) {
+      if (kernel == 0 && fused_[0]) {
+        for (int pr = 0; pr < 2; ++pr)
+          for (int f = 0; f < 2; ++f)
+            launch_gs_fused_batched<float>(fix(gsf_[0][pr].w[f]), s_, false, f == 1);
+        launches = 2;
+      } else if (kernel == 0) {
+        for (int c = 0; c < 4; ++c)
+          for (int f = 0; f < 2; ++f)
+            launch_gs_batched<float>(fix(gs_[0][c].w[f]), s_, by_gs_[0], false, f == 1);
+        launches = 4;
+      } else {
+        for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(res_[0].w[f]), s_, by_res_[0], f == 1);
+        launches = 1;
+      }
     }
+    MCW_HIP(hipEventRecord(e1, s_));
+    MCW_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    MCW_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return {ms / reps, launches};
   }
 
  private:
