@@ -224,3 +224,35 @@ def test_batched_colour_passes_match_single_cg_bit_for_bit(tmp_path, monkeypatch
     for lam, ref, info in zip(lams, singles, infos):
         assert info["rel_residual"] <= 1e-10
         assert torch.equal(lam, ref)
+
+
+def test_64_member_ensemble_sampled_against_the_oracle():
+    """The benchmark's ensemble (64 seeded members, 64^2..512^2 x 8..16, a3 up
+    to 10) in one batch with the benchmark's options and launch shapes, solved
+    to 1e-10: every member converges, the seven 64x64x8 members match the
+    oracle's direct solve, and on the largest member (512x512x16) the
+    oracle's f - K lambda of the GPU's lambda on two windows is small."""
+    from tests.test_gpu_solve import _window_residual
+    mcwind = _mcw()
+    print("[case] 64-member ensemble, sampled", flush=True)
+    probs = [inputs.c4_member(m) for m in range(64)]
+    grids, u0s = [list(t) for t in zip(*[mcwind.grid_from_problem(p, rtol=1e-10) for p in probs])]
+    lams, _, infos, st = mcwind.solve_batch(grids, u0s, want_u=False)
+    assert st == "MCW_OK"
+    assert max(i["rel_residual"] for i in infos) <= 1e-10
+    small = [m for m, p in enumerate(probs) if p.dims == (64, 64, 8)]
+    assert len(small) == 7
+    for m in small:
+        ref, _, _ = osolve.solve(probs[m], rtol=1e-14)
+        err = gc.rel_err(lams[m].cpu().numpy(), ref)
+        print(f"  member {m}: lambda rel err {err:.1e}", flush=True)
+        assert err < 1e-7
+    big = max(range(64), key=lambda m: probs[m].n_nodes)
+    p = probs[big]
+    lam_h = lams[big].cpu().numpy()
+    fn = infos[big]["f_norm"]
+    for (i0, i1, j0, j1) in [(0, 16, 0, 16), (250, 270, 300, 318)]:
+        r, _ = _window_residual(p, lam_h, i0, i1, j0, j1)
+        assert np.abs(r).max() <= 1e-10 * fn
+    for g in grids:
+        g.close()
