@@ -387,17 +387,33 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_baseline_cold_solve(p):
+    """cpu_baseline leg of the configs workload: the FP64 oracle's cold
+    Jacobi-PCG solve of the whole problem to relative residual 1e-8 on one host
+    thread, with its assembly of K and f.  Returns the oracle's lambda (for the
+    error of the GPU's lambda) and the timing row."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import solve as osolve
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        lam_o, _, oinfo = osolve.solve(p, method="cg", rtol=1e-8)
+        t = time.perf_counter() - t0
+    return lam_o, {"s": round(t, 2), "Mnodes/s": round(p.n_nodes / t / 1e6, 4),
+                   "kind": "oracle", "cores": 1, "host_cpus": os.cpu_count(),
+                   "iterations": oinfo["iterations"], "method": oinfo["method"]}
+
+
 def bench_configs(args):
     """The smaller configurations: 32x32x8 Gaussian hill, 256x256x16 with 40
     hills, and 512x512x15 fractal terrain (500 m relief).  GPU solves in both
     precisions to relative residual 1e-8 from lambda = 0, with the V-cycle rate
     (also with the coarsened spacing in the layer test of the coarsening rule,
-    as printed); on the first two, the oracle's cold Jacobi-PCG solve (host
-    CPU) and the error of the GPU's lambda against it."""
+    as printed); on the first two, the cpu_baseline leg of this workload: the
+    oracle's cold Jacobi-PCG solve (host CPU) and the error of the GPU's lambda
+    against it (left out with --no-cpu-baseline)."""
     import torch
-    from threadpoolctl import threadpool_limits
 
-    from oracle import solve as osolve
     from paper_2101_08453_amd import inputs, mcwind
     rows = []
     for name, make, oracle in (("32x32x8 gaussian hill", inputs.c1, True),
@@ -427,15 +443,10 @@ def bench_configs(args):
             row[key + "_lambda"] = lam.cpu().numpy()
             g.close()
             log(f"{name} {key}: {ms:.2f} ms, {info['cycles']} cycles, rho {info['rho']:.3f}")
+        oracle = oracle and not args.no_cpu_baseline
         if oracle:
             log(f"{name}: GPU done, oracle running")
-            with threadpool_limits(limits=1):
-                t0 = time.perf_counter()
-                lam_o, _, oinfo = osolve.solve(p, method="cg", rtol=1e-8)
-                t = time.perf_counter() - t0
-            row["oracle"] = {"s": round(t, 2), "Mnodes/s": round(p.n_nodes / t / 1e6, 4),
-                             "cores": 1, "host_cpus": os.cpu_count(),
-                             "iterations": oinfo["iterations"], "method": oinfo["method"]}
+            lam_o, row["oracle"] = cpu_baseline_cold_solve(p)
         for key in ("fp32_refine", "fp64", "fp64_coarsened_spacing"):
             lg = row.pop(key + "_lambda")
             if oracle:
