@@ -31,6 +31,9 @@ if ROOT not in sys.path:
 
 METRIC = "Mnodes/s solved to rel. residual 1e-8 (FP32+refine vs FP64); stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# bytes of one node's FP32 stencil: 25 stored coefficients (the diagonal and
+# the coupling to the node below are formed from the others)
+ST32_BYTES = 100.0
 PROFILE = os.path.join(ROOT, "profiles", "gs_fused_f32_c3_3000x3000x15.md")
 
 
@@ -109,17 +112,17 @@ def kernel_table(g, stream, n_free):
         g.run_kernel(0, kernel, 1)  # warm
         return time_on_stream(stream, lambda: g.run_kernel(0, kernel, reps), 1) / (reps * launches_per_rep)
 
-    # a sweep updates every free node once: the 26 stored FP32 off-diagonal
-    # coefficients (104 B; the diagonal is formed from them), f (4 B), and x read
-    # and written (8 B) = 116 B.  It runs as 4 colour-pass launches, or as 2 when
-    # the level uses the fused two-colour pass.
+    # a sweep updates every free node once: the 25 stored FP32 coefficients
+    # (100 B; the diagonal and the coupling to the node below are formed from
+    # them), f (4 B), and x read and written (8 B) = 112 B.  It runs as 4
+    # colour-pass launches, or as 2 when the level uses the fused two-colour pass.
     launches = 2 if g.tile_rows(0)[0] == 0 else 4
     ms = timed("smooth", 8, launches)
-    b = 116.0 * n_free / launches
+    b = (ST32_BYTES + 12.0) * n_free / launches
     out["gs_colour_pass_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6,
                                  "launches_per_sweep": launches}
     ms = timed("residual", 4)
-    b = (104.0 + 4 + 4 + 4) * N  # stencil, x, f, r
+    b = (ST32_BYTES + 4 + 4 + 4) * N  # stencil, x, f, r
     out["residual_f32"] = {"ms": ms, "bytes": b, "GB/s": b / ms / 1e6}
     ms = timed("restrict", 4)
     b = 4.0 * N + 4.0 * Nc
@@ -285,16 +288,16 @@ def bench_c4(args):
         cyc = [i["cycles"] for i in infos]
         log(f"batched fp32_refine: {ms_batch:.1f} ms, cycles {min(cyc)}..{max(cyc)}, {status}")
         # the batched colour pass over every member's finest level: one sweep is
-        # two two-colour launches (or four one-colour ones); each free node's 26
-        # FP32 off-diagonals, f, and x read and written once per sweep (116 B).
+        # two two-colour launches (or four one-colour ones); each free node's 25
+        # stored FP32 coefficients, f, and x read and written once per sweep (112 B).
         # Device time per sweep from HIP events on the batch's stream.
         n_free = sum(int(np.prod([d - 1 for d in p.dims[:2]])) * p.dims[2] for p in probs)
         mcwind.run_kernel_batch(g32, "smooth", 1)
         ms_sweep, lps = mcwind.run_kernel_batch(g32, "smooth", 16)
         mcwind.run_kernel_batch(g32, "residual", 1)
         ms_res, _ = mcwind.run_kernel_batch(g32, "residual", 16)
-        b_sweep = 116.0 * n_free
-        b_res = 116.0 * sum(p.n_nodes for p in probs)
+        b_sweep = (ST32_BYTES + 12.0) * n_free
+        b_res = (ST32_BYTES + 12.0) * sum(p.n_nodes for p in probs)
         kname = ("gs_fused_batched<float, false, 0> (two colour passes per launch)" if lps == 2
                  else "gs_pass_batched<float, 0> (one colour pass per launch)")
         batch_roof = {"bound": "hbm", "kernel": kname, "launches_per_sweep": lps,

@@ -144,7 +144,7 @@ typedef struct {
                                  needs nu_pre == nu_post */
   int32_t smoother;           /* mcw_smoother; default MCW_SMOOTH_POINT */
   int32_t stencil_fp16;       /* FP32_REFINE only.  0 (default): the V-cycle's stencils are FP32.
-                                 1: they are kept in FP16 (52 instead of 104 bytes per node), each
+                                 1: they are kept in FP16 (50 instead of 100 bytes per node), each
                                  level's off-diagonals divided by a power of two above their
                                  largest magnitude; the V-cycle still computes in FP32 and the
                                  refinement in FP64, so the solution meets rtol as before.  One
@@ -339,7 +339,11 @@ mcw_status mcw_level_info(const mcw_handle* h, int32_t l, int32_t dims[3], int32
  * o*N_l + n holds K[n, n + offset(o)] with o = (di+1) + 3(dj+1) + 9(dk+1), in
  * natural node order.  prec = MCW_FP64 gives the FP64 operator (available in
  * FP64 handles; for FP32_REFINE handles only level 0, recomputed), MCW_FP32_REFINE the
- * FP32 copy used by the V-cycles (out is then float*). */
+ * FP32 operator of the V-cycles (out is then float*): off-diagonals rounded once
+ * from FP64, except that the coupling to the node below (o = 4) is the node
+ * below's rounded coupling to the node above (o = 22; zero on the bottom plane),
+ * and the diagonal minus the off-diagonal sum; with stencil_fp16 the FP16 values
+ * times the level's scale, defined the same way. */
 mcw_status mcw_get_stencil(mcw_handle* h, int32_t l, int32_t prec, void* out);
 
 /* The smoother of Sec. 3 (vertical Gauss-Seidel sweeps in four horizontal

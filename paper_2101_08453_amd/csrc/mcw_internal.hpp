@@ -128,33 +128,37 @@ __host__ __device__ inline size_t st_entry<double>(size_t p, int o) {
   return ((p >> 6) * G + o / 2) * (size_t)128 + (p & 63) * 2 + (o % 2);
 }
 
-// FP32 stencils store only the 26 off-diagonal coefficients: the diagonal of
-// the FP32 operator is minus their sum (stencil_diag), so it is formed where
-// it is used instead of being read.  Per 64 consecutive nodes: six groups of
-// four floats (slots 0-23) and one group of two (slots 24, 25), each
-// interleaved over the 64 nodes; 104 B per node.
-constexpr int SW32 = 26;
-__host__ __device__ constexpr int slot32(int o) { return o < 13 ? o : o - 1; }  // o != 13
+// FP32 stencils store 25 of the 26 off-diagonal coefficients.  The diagonal
+// of the FP32 operator is minus the sum of the off-diagonals (stencil_diag),
+// and the coupling to the node below in the same column (o = 4) is the
+// coupling of that node to the one above it (its o = 22): the column coupling
+// of the FP32 operator is symmetric by construction, and zero below the
+// bottom plane.  Both are formed where they are used instead of being read; a
+// thread marching up a column already holds the o = 22 value of the node
+// below.  Per 64 consecutive nodes: six groups of four floats (slots 0-23)
+// and one single float (slot 24), each interleaved over the 64 nodes; 100 B
+// per node.
+constexpr int SW32 = 25;
+__host__ __device__ constexpr bool stored32(int o) { return o != 4 && o != 13; }
+__host__ __device__ constexpr int slot32(int o) { return o < 4 ? o : (o < 13 ? o - 1 : o - 2); }
 template <>
 __host__ __device__ inline size_t st_entry<float>(size_t p, int o) {
   const int s = slot32(o);
   const size_t base = (p >> 6) * (size_t)(64 * SW32);
-  return s < 24 ? base + (size_t)(s >> 2) * 256 + (p & 63) * 4 + (s & 3)
-                : base + 1536 + (p & 63) * 2 + (s - 24);
+  return s < 24 ? base + (size_t)(s >> 2) * 256 + (p & 63) * 4 + (s & 3) : base + 1536 + (p & 63);
 }
 
-// FP16 stencils (option stencil_fp16): the same 26 off-diagonal coefficients,
+// FP16 stencils (option stencil_fp16): the same 25 stored coefficients,
 // divided by a power of two s per level (the level's largest magnitude rounded
 // up) and rounded once to FP16 (below 2^-14 to zero).  Per 64 consecutive nodes: three
-// groups of eight halves (slots 0-23) and one of two (slots 24, 25); 52 B per
+// groups of eight halves (slots 0-23) and one single half (slot 24); 50 B per
 // node.  The kernels compute with the scaled values and scale f and r by 1/s
 // and s, both exact.
-constexpr int SW16 = 26;
+constexpr int SW16 = 25;
 __host__ __device__ inline size_t st_entry16(size_t p, int o) {
   const int s = slot32(o);
   const size_t base = (p >> 6) * (size_t)(64 * SW16);
-  return s < 24 ? base + (size_t)(s >> 3) * 512 + (p & 63) * 8 + (s & 7)
-                : base + 1536 + (p & 63) * 2 + (s - 24);
+  return s < 24 ? base + (size_t)(s >> 3) * 512 + (p & 63) * 8 + (s & 7) : base + 1536 + (p & 63);
 }
 
 // A level's stencil as the kernels see it: the array, whether it holds FP16

@@ -41,11 +41,13 @@ __device__ __forceinline__ StLayout dev_layout(int NX, int NY) {
 // with non-temporal loads: a pass streams each stencil value once, so it
 // should not displace the x values that neighbouring columns reuse.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-// FP32: the 26 stored off-diagonal coefficients into a[o], o != 13, and the
-// diagonal a[13] formed from them (the same value the rounding kernel defines).
-__device__ __forceinline__ void load_stencil_nt(const float* __restrict__ st, size_t p, float a[SW]) {
+// FP32: the 25 stored coefficients into a[o], the column coupling below a[4]
+// from `below` (the o = 22 coefficient of the node below, 0 on the bottom
+// plane), and the diagonal a[13] formed from them (the same values that
+// mcw_get_stencil reports).
+__device__ __forceinline__ void load_stencil_nt(const float* __restrict__ st, size_t p, float a[SW],
+                                                float below) {
   const float* base = st + (p >> 6) * (size_t)(64 * SW32);
   const f32x4* v = reinterpret_cast<const f32x4*>(base) + (p & 63);
   float b[SW32];
@@ -54,14 +56,16 @@ __device__ __forceinline__ void load_stencil_nt(const float* __restrict__ st, si
     const f32x4 t = __builtin_nontemporal_load(v + g * 64);
     b[4 * g] = t.x; b[4 * g + 1] = t.y; b[4 * g + 2] = t.z; b[4 * g + 3] = t.w;
   }
-  const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(base + 1536) + (p & 63));
-  b[24] = t.x; b[25] = t.y;
+  b[24] = __builtin_nontemporal_load(base + 1536 + (p & 63));
 #pragma unroll
   for (int o = 0; o < 27; ++o)
-    if (o != 13) a[o] = b[slot32(o)];
+    if (stored32(o)) a[o] = b[slot32(o)];
+  a[4] = below;
   a[13] = stencil_diag(a);
 }
-__device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, size_t p, double a[SW]) {
+// FP64: all 27 coefficients are stored; `below` is not used.
+__device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, size_t p, double a[SW],
+                                                double /*below*/) {
   const f64x2* v = reinterpret_cast<const f64x2*>(st) + (p >> 6) * (SW / 2) * 64 + (p & 63);
 #pragma unroll
   for (int g = 0; g < SW / 2; ++g) {
@@ -72,11 +76,12 @@ __device__ __forceinline__ void load_stencil_nt(const double* __restrict__ st, s
 template <class T>
 __device__ __forceinline__ T load_nt(const T* p) { return __builtin_nontemporal_load(p); }
 
-// FP16 stencils: the 26 scaled off-diagonals as FP32 into a[o], o != 13, and
-// the diagonal formed from them as for FP32 stencils.
+// FP16 stencils: the 25 stored scaled coefficients as FP32 into a[o], a[4]
+// from `below` (scaled as well) and the diagonal formed from them, as for FP32
+// stencils.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st, size_t p, float a[SW]) {
+__device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st, size_t p, float a[SW],
+                                                 float below) {
   const _Float16* base = st + (p >> 6) * (size_t)(64 * SW16);
   const f16x8* v = reinterpret_cast<const f16x8*>(base) + (p & 63);
   float b[SW16];
@@ -86,12 +91,11 @@ __device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st
 #pragma unroll
     for (int e = 0; e < 8; ++e) b[8 * g + e] = (float)t[e];
   }
-  const f16x2 t = __builtin_nontemporal_load(reinterpret_cast<const f16x2*>(base + 1536) + (p & 63));
-  b[24] = (float)t.x;
-  b[25] = (float)t.y;
+  b[24] = (float)__builtin_nontemporal_load(base + 1536 + (p & 63));
 #pragma unroll
   for (int o = 0; o < 27; ++o)
-    if (o != 13) a[o] = b[slot32(o)];
+    if (stored32(o)) a[o] = b[slot32(o)];
+  a[4] = below;
   a[13] = stencil_diag(a);
 }
 
@@ -99,13 +103,29 @@ __device__ __forceinline__ void load_stencil_h16(const _Float16* __restrict__ st
 // FP16 values scaled by 1/sc.  Each launch, single or batched, runs the
 // instance of its stencils' format, so an FP32 or FP64 kernel carries no FP16
 // code (a format chosen per job at run time cost the batched FP32 kernels up
-// to 40 registers per lane).
+// to 40 registers per lane).  `below` is the o = 22 coefficient of the node
+// under p, in the units of a (FP32 and FP16 formats; FP64 stores it).
 template <class T, int SF>
-__device__ __forceinline__ void load_stencil(const ColJob& J, size_t p, T a[SW]) {
+__device__ __forceinline__ void load_stencil(const ColJob& J, size_t p, T a[SW], T below) {
   if constexpr (sizeof(T) == 4 && SF == 1)
-    load_stencil_h16(static_cast<const _Float16*>(J.st), p, a);
+    load_stencil_h16(static_cast<const _Float16*>(J.st), p, a, below);
   else
-    load_stencil_nt(static_cast<const T*>(J.st), p, a);
+    load_stencil_nt(static_cast<const T*>(J.st), p, a, below);
+}
+
+// The o = 22 coefficient (the coupling to the node above) of node p, in the
+// units load_stencil gives: what a column march that starts above p, or runs
+// downwards, needs for the a[4] of the node above p.  Zero for FP64 stencils,
+// which store a[4] themselves.
+template <class T, int SF>
+__device__ __forceinline__ T up_coupling(const ColJob& J, size_t p) {
+  if constexpr (sizeof(T) == 8) {
+    return T(0);
+  } else if constexpr (SF == 1) {
+    return (float)static_cast<const _Float16*>(J.st)[st_entry16(p, 22)];
+  } else {
+    return static_cast<const float*>(J.st)[st_entry<float>(p, 22)];
+  }
 }
 
 // v times the job's scale factor s, except for format 0 (T stencils, s = 1).
@@ -186,6 +206,9 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
     for (int k = kl; k < NZ; ++k) rl[(size_t)k * plane + cols[4]] = T(0);
   }
   T a_up = T(0);  // the coupling of the node below to this one
+  // the forward march carries the node below's upward coupling, the a[4] of
+  // the next node (the bottom free node's comes from the plane under it)
+  T below = (!REV && kf > 0) ? up_coupling<T, SF>(J, L.node(i, j, kf - 1)) : T(0);
   // rolling window of the 3 x 9 neighbour values: xl the plane already passed,
   // x0 the current plane, xn the plane ahead
   T xl[9], x0[9], xn[9];
@@ -203,8 +226,10 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
     const int ka = REV ? (k > 0 ? k - 1 : 0) : (k + 1 < NZ ? k + 1 : NZ - 1);
 #pragma unroll
     for (int q = 0; q < 9; ++q) xn[q] = x[(size_t)ka * plane + cols[q]];
+    if (REV) below = k > 0 ? up_coupling<T, SF>(J, L.node(i, j, k - 1)) : T(0);
     T a[SW];
-    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    load_stencil<T, SF>(J, L.node(i, j, k), a, below);
+    below = a[22];
     T s = scaled<SF>(load_nt(f + (size_t)k * plane + cols[4]), J.isc);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
@@ -271,12 +296,14 @@ __device__ __forceinline__ void line_column(const ColJob& J, int i, int j, T* ls
     }
   }
   T cprev = T(0), dprev = T(0);
+  T below = kf > 0 ? up_coupling<T, SF>(J, L.node(i, j, kf - 1)) : T(0);
   for (int k = kf; k <= kl; ++k) {
     const int ka = k + 1 < NZ ? k + 1 : NZ - 1;
 #pragma unroll
     for (int q = 0; q < 9; ++q) xa[q] = x[(size_t)ka * plane + cols[q]];
     T a[SW];
-    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    load_stencil<T, SF>(J, L.node(i, j, k), a, below);
+    below = a[22];
     T s = scaled<SF>(load_nt(f + (size_t)k * plane + cols[4]), J.isc);
     const bool first = k == kf, last = k == kl;
 #pragma unroll
@@ -457,12 +484,14 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   }
   // every k is computed (all loads are in range) so that the loads of a plane
   // are issued together; rows of fixed planes are then set to zero
+  T below = T(0);  // the node below's upward coupling: a[4] of plane k
   for (int k = 0; k < NZ; ++k) {
     const size_t pp = (size_t)(k + 1 < NZ ? k + 1 : NZ - 1) * plane;
 #pragma unroll
     for (int q = 0; q < 9; ++q) xp[q] = x[pp + cols[q]];
     T a[SW];
-    load_stencil<T, SF>(J, L.node(i, j, k), a);
+    load_stencil<T, SF>(J, L.node(i, j, k), a, below);
+    below = a[22];
     T s = f ? scaled<SF>(load_nt(f + (size_t)k * plane + own), J.isc) : T(0);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
@@ -861,9 +890,11 @@ __global__ __launch_bounds__(256) void rap_kernel(const double* __restrict__ stf
   stc[st_entry<double>(outpos, 27)] = 0.0;
 }
 
-// FP32 copy of an FP64 stencil.  The off-diagonal entries are rounded, and
-// the diagonal is set to minus their (rounded) sum, so that constants stay in
-// the null space of the unconstrained FP32 operator as they are for K.
+// FP32 copy of an FP64 stencil: the stored off-diagonal entries (all but the
+// coupling to the node below, which is the node below's upward one) rounded
+// once.  The kernels form the diagonal as minus the sum of the off-diagonals,
+// so that constants stay in the null space of the unconstrained FP32 operator
+// as they are for K.
 __global__ __launch_bounds__(256) void round_stencil_kernel(const double* __restrict__ s64,
                                                             float* __restrict__ s32, int NX, int NY,
                                                             size_t N) {
@@ -873,12 +904,13 @@ __global__ __launch_bounds__(256) void round_stencil_kernel(const double* __rest
   const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
 #pragma unroll
   for (int o = 0; o < 27; ++o)
-    if (o != 13) s32[st_entry<float>(p, o)] = (float)s64[st_entry<double>(p, o)];
+    if (stored32(o)) s32[st_entry<float>(p, o)] = (float)s64[st_entry<double>(p, o)];
 }
 
-// FP16 copy: each off-diagonal divided by the level scale (exact) and rounded
-// once, from FP64, to the nearest FP16 value; values below the smallest normal
-// FP16 number (2^-14, i.e. below 2^-14 of the level's scale) are stored as zero.
+// FP16 copy: each stored off-diagonal (as for FP32) divided by the level scale
+// (exact) and rounded once, from FP64, to the nearest FP16 value; values below
+// the smallest normal FP16 number (2^-14, i.e. below 2^-14 of the level's
+// scale) are stored as zero.
 // This is the definition the tests check; it does not depend on how the
 // hardware treats FP16 subnormals.
 __global__ __launch_bounds__(256) void round_stencil16_kernel(const double* __restrict__ s64,
@@ -890,7 +922,7 @@ __global__ __launch_bounds__(256) void round_stencil16_kernel(const double* __re
   const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
 #pragma unroll
   for (int o = 0; o < 27; ++o)
-    if (o != 13) {
+    if (stored32(o)) {
       const double v = s64[st_entry<double>(p, o)] * inv_scale;
       s16[st_entry16(p, o)] = fabs(v) < 0x1p-14 ? (_Float16)0.0 : (_Float16)v;
     }
@@ -940,12 +972,18 @@ __global__ __launch_bounds__(256) void unsplit16_kernel(const _Float16* __restri
   if (gid >= N * 27) return;
   const size_t o = gid / N, n = gid % N;
   const StLayout L = dev_layout(NX, NY);
-  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+  const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+  const size_t p = L.node(i, j, k);
+  // the coupling to the node below is that node's upward one (0 on the bottom plane)
+  const float below = k > 0 ? (float)s[st_entry16(L.node(i, j, k - 1), 22)] : 0.f;
   if (o == 13) {
     float a[27];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) a[q] = q == 13 ? 0.f : (float)s[st_entry16(p, q)];
+    for (int q = 0; q < 27; ++q) a[q] = stored32(q) ? (float)s[st_entry16(p, q)] : 0.f;
+    a[4] = below;
     out[gid] = stencil_diag(a) * scale;
+  } else if (o == 4) {
+    out[gid] = below * scale;
   } else {
     out[gid] = (float)s[st_entry16(p, (int)o)] * scale;
   }
@@ -958,13 +996,21 @@ __global__ __launch_bounds__(256) void unsplit_kernel(const T* __restrict__ s, T
   if (gid >= N * 27) return;
   const size_t o = gid / N, n = gid % N;
   const StLayout L = dev_layout(NX, NY);
-  const size_t p = L.node((int)(n % NX), (int)((n / NX) % NY), (int)(n / ((size_t)NX * NY)));
+  const int i = (int)(n % NX), j = (int)((n / NX) % NY), k = (int)(n / ((size_t)NX * NY));
+  const size_t p = L.node(i, j, k);
   if constexpr (sizeof(T) == 4) {
+    // the coupling to the node below is that node's upward one (0 on the bottom plane)
+    const float below = k > 0 ? s[st_entry<float>(L.node(i, j, k - 1), 22)] : 0.f;
     if (o == 13) {
       float a[27];
 #pragma unroll
-      for (int q = 0; q < 27; ++q) a[q] = q == 13 ? 0.f : s[st_entry<float>(p, q)];
+      for (int q = 0; q < 27; ++q) a[q] = stored32(q) ? s[st_entry<float>(p, q)] : 0.f;
+      a[4] = below;
       out[gid] = stencil_diag(a);
+      return;
+    }
+    if (o == 4) {
+      out[gid] = below;
       return;
     }
   }

@@ -29,7 +29,9 @@ def _mcw():
 def test_fp16_stencils_are_the_rounded_galerkin_stencils(name):
     """Every level: off-diagonals = fp16(a / s) * s, rounded once from FP64, with
     s = 2^(floor(log2 max|a|) + 1), and zero where |a / s| < 2^-14 (below the FP16
-    normal range); the diagonal minus their sum (FP64 sum, rounded once)."""
+    normal range); the coupling to the node below (o = 4) is the node below's
+    coupling to the node above (o = 22; zero on the bottom plane); the diagonal
+    minus their sum (FP64 sum, rounded once)."""
     mcwind = _mcw()
     p = gc.problem(name)
     print(f"[case] fp16 stencil {name}", flush=True)
@@ -45,6 +47,10 @@ def test_fp16_stencils_are_the_rounded_galerkin_stencils(name):
         v = s64[off] / s
         v = np.where(np.abs(v) < 2.0 ** -14, 0.0, v)
         want = v.astype(np.float16).astype(np.float32) * np.float32(s)
+        # o = 4 is row 4 of the off-diagonal rows: the o = 22 row (row 21) one plane down
+        nxy = g16.level_shape(l)[1] * g16.level_shape(l)[2]
+        want[4] = 0.0
+        want[4, nxy:] = want[21, :-nxy]
         assert np.array_equal(s16[off], want), f"level {l}"
         diag = (-(want / np.float32(s)).astype(np.float64).sum(axis=0)).astype(np.float32) * np.float32(s)
         assert np.array_equal(s16[13], diag), f"level {l}"

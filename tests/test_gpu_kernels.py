@@ -93,14 +93,27 @@ def test_hierarchy_and_galerkin_operators(name, rule):
 
 @pytest.mark.parametrize("name", ["c1", "ragged"])
 def test_fp32_stencils_round_off_diagonals_and_keep_row_sums(name):
+    """The FP32 operator: off-diagonals rounded once from FP64, except the
+    coupling to the node below (o = 4), which is the node below's rounded
+    coupling to the node above (o = 22; zero on the bottom plane), so the
+    column coupling is symmetric; the diagonal is minus the off-diagonal sum
+    (FP64 sum, rounded once)."""
     g64, _ = _grid(name, precision="fp64", coarse_direct_max=60)
     g32, _ = _grid(name, precision="fp32_refine", coarse_direct_max=60)
     for l in range(g64.num_levels()):
         s64 = g64.stencil(l, "fp64").cpu().numpy()
         s32 = g32.stencil(l, "fp32_refine").cpu().numpy()
+        stored = np.ones(27, dtype=bool)
+        stored[[4, 13]] = False
+        assert np.array_equal(s32[stored], s64[stored].astype(np.float32)), f"level {l}"
+        want4 = np.zeros_like(s32[4])
+        want4[1:] = s32[22][:-1]
+        assert np.array_equal(s32[4], want4), f"level {l}"
+        # K is symmetric, so this is the rounding of its own o = 4 entry up to
+        # the FP64 assembly's last bits
+        assert np.allclose(s32[4], s64[4], rtol=2.0 ** -23, atol=0.0), f"level {l}"
         off = np.ones(27, dtype=bool)
         off[13] = False
-        assert np.array_equal(s32[off], s64[off].astype(np.float32)), f"level {l}"
         diag = (-s32[off].astype(np.float64).sum(axis=0)).astype(np.float32)
         assert np.array_equal(s32[13], diag)
 
