@@ -587,6 +587,21 @@ __device__ __forceinline__ void elem_tile_body(const TileJob& A, int bx, int by,
             y[0][a] -= tmp[a];
             y[CH - 1][a] = -tmp[a];
           }
+          // the recovered wind u0 + diag(c) grad lambda(centre), as recover_body
+          // computes it, written by the tile that owns the element's lower
+          // corner node (each element exactly once)
+          if (A.uout && ex >= 1 && ey >= 1) {
+            double cj[3][3], r[3][3], g[3];
+            centre_jacobian(xe, cj);
+            const double det = adjugate(cj[0], cj[1], cj[2], r);
+            centre_ref_grad(ve, g);
+            const double idet = 1.0 / det;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const double gx = (g[0] * r[0][d] + g[1] * r[1][d] + g[2] * r[2][d]) * idet;
+              A.uout[d * E + e] = u[d] + A.c[d] * gx;
+            }
+          }
         }
       }
     }
@@ -956,8 +971,9 @@ size_t tile_count(const Dims& d) {
 }
 
 void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam, double* D,
-                           double* partials, hipStream_t s) {
+                           double* partials, hipStream_t s, double* u) {
   TileJob A{};
+  A.uout = u;
   A.X = G.X;
   A.Y = G.Y;
   A.Z = G.Z;
@@ -993,12 +1009,12 @@ void launch_structure_check(const double* X, const double* Y, const Dims& d, int
 }
 
 void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
-                       double* partials, size_t* n_part) {
+                       double* partials, size_t* n_part, double* u) {
   const size_t tiles = tile_count(h.d);
   if (partials) need_partials(2 * tiles, h.n_partials);
   GridRef G{h.X.as<double>(), h.Y.as<double>(), h.Z.as<double>(), h.d, {h.c[0], h.c[1], h.c[2]},
             h.faces, h.terrain ? 1 : 0, nullptr};
-  launch_divergence_ref(G, u0, lam, D, partials, h.stream);
+  launch_divergence_ref(G, u0, lam, D, partials, h.stream, u);
   if (n_part) *n_part = tiles;
 }
 

@@ -303,6 +303,7 @@ struct TileJob {  // element-tile kernels (matrix-free apply/residual, rhs, dive
   const double* f;   // right-hand side (residual)
   const double* ue;  // element 3-vectors (rhs, divergence, adjoint scatter)
   double* out;       // nodal output
+  double* uout;      // divergence: when not null, the recovered wind (element 3-vectors)
   double* partials;  // [channel][block] sums of squares over the free nodes
   int nx, ny, nz;
   double c[3];
@@ -421,8 +422,10 @@ void launch_assemble_stencil(const mcw_handle& h, double* st64);
 void launch_apply(const mcw_handle& h, const double* x, const double* f, double* out, int mode,
                   double* partials, size_t* n_part);
 void launch_rhs(const mcw_handle& h, const double* u0, double* f, double* partials, size_t* n_part);
+// With u not null the same launch also writes the recovered wind u = u0 +
+// diag(c) grad lambda(centre), bit for bit what launch_recover writes.
 void launch_divergence(const mcw_handle& h, const double* u0, const double* lam, double* D,
-                       double* partials, size_t* n_part);
+                       double* partials, size_t* n_part, double* u = nullptr);
 // The geometry the element-tile kernels read, without a handle: node
 // coordinates in place, dimensions, coefficients a_d^-2 and Gamma.
 struct GridRef {
@@ -441,7 +444,7 @@ void launch_structure_check(const double* X, const double* Y, const Dims& d, int
                             hipStream_t s);
 // Weak divergence with 2 partial sums per block written to partials[0 .. 2 tile_count).
 void launch_divergence_ref(const GridRef& G, const double* u0, const double* lam, double* D,
-                           double* partials, hipStream_t s);
+                           double* partials, hipStream_t s, double* u = nullptr);
 void launch_recover(const mcw_handle& h, const double* u0, const double* lam, double* u);
 // Steps around the solve (coupling_kernels.hip)
 bool launch_coarse_check(const mcw_handle& h, const mcw_coarse_wind& cw);

@@ -692,8 +692,8 @@ mcw_status solve_impl(mcw_handle& h, const double* u0, double* lam, double* u, m
   MCW_HIP(hipEventRecord(h.ev[2], h.stream));
   double div[2] = {0.0, 0.0};
   if (st == MCW_OK || st == MCW_NOT_CONVERGED) {
-    if (u) launch_recover(h, u0, lam, u);
-    launch_divergence(h, u0, lam, h.t64.as<double>(), h.partials.as<double>(), &np);
+    // one element-tile launch recovers u (when wanted) and checks the divergence
+    launch_divergence(h, u0, lam, h.t64.as<double>(), h.partials.as<double>(), &np, u);
     reduce_to_host(h, np, 2, div);
   } else if (u) {
     MCW_HIP(hipMemcpyAsync(u, u0, 3 * E * sizeof(double), hipMemcpyDeviceToDevice, h.stream));

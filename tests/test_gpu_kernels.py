@@ -47,6 +47,20 @@ def test_rhs_matches_one_point_quadrature(name):
     assert gc.rel_err(f, ref) < 1e-13
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("name", gc.CASES)
+def test_solve_recovers_the_wind_as_the_recovery_entry_point(name, precision):
+    """The solve recovers u in its divergence-check launch: the same bits as
+    mcw_recover on the solve's lambda, and the same divergence as
+    mcw_divergence."""
+    g, u0 = _grid(name, precision=precision, rtol=1e-10)
+    lam, u, info = g.solve(u0)
+    assert info["status"] == "MCW_OK"
+    assert torch.equal(u, g.recover(u0, lam))
+    _, rel = g.divergence(u0, lam)
+    assert rel == info["rel_divergence"]
+
+
 @pytest.mark.parametrize("name", gc.CASES)
 def test_recovery_and_divergence(name):
     g, u0 = _grid(name)
