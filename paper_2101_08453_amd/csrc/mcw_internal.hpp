@@ -251,8 +251,9 @@ struct ColJob {  // smoother colour pass, residual
   double* part;          // per-block partial sums of a batched residual with a dot product
   int h16;               // the stencil holds FP16 values scaled by 1/sc (FP32 V-cycles only)
   float sc, isc;         // sc and 1/sc; 1 for FP32 and FP64 stencils
-  void* rlast;           // forward pass of colour (1,1) ending a sweep: also write r there
-  int skip11;            // residual: colour (1,1) columns already hold r (written by rlast)
+  void* rlast;           // forward pass ending a sweep: also write r of this colour's columns
+  void* rside;           // forward (1,1) pass ending a sweep: side sums for the (0,1) columns
+  int skip11;            // residual: 1, the (1,1) columns already hold r; 2, every odd row does
 };
 
 struct FusedJob {  // two colour passes of the same rows, one block per row (batched)
@@ -467,13 +468,17 @@ void launch_recover_batched(const WorkList& W, hipStream_t s);
 // Multigrid kernels (templated on the V-cycle precision)
 // line_buf: null for the point smoother; for the vertical line smoother a
 // level-sized scratch vector (the elimination coefficients)
-// r_last: when given (forward sweeps only), the pass of the last colour, (1,1),
-// also writes r = f - K x on its columns, which no later pass of the sweep
-// changes; launch_residual with last_colour_done then computes only the others.
+// r_last: when given (forward sweeps only), the sweep also leaves r = f - K x
+// on the columns whose residual it already knows: those of the last colour,
+// (1,1), which no later pass changes (returns 1), and, where the odd rows run
+// as one two-colour launch of the point smoother, those of (0,1) too, whose
+// only later change is the (1,1) pass of the same launch (returns 2: every odd
+// row holds r).  launch_residual given that value computes only the rest.
+// Returns 0 without r_last.
 template <class T>
-void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
-                         hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr,
-                         T* r_last = nullptr);
+int launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
+                        hipStream_t s, int by = 0, bool reverse = false, T* line_buf = nullptr,
+                        T* r_last = nullptr);
 // preconditioned conjugate gradients; sc = device scalars {r.z, alpha, beta, r.r}
 void launch_cg_reset(double* sc, hipStream_t s);
 template <class T>
@@ -490,10 +495,13 @@ void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, 
 template <class T>
 void launch_neg_apply_dot(const Dims& d, const Faces& fc, StRef st, const T* p, T* q,
                           double* partials, size_t cap, size_t* n_part, hipStream_t s, int by);
+// A V-cycle residual job after a sweep that left r on some columns (mode 1:
+// the (1,1) ones; 2: every odd row, and the job then covers the even rows only).
+void residual_skip(ColJob& J, int mode);
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
                      double* partials, size_t* n_part, hipStream_t s, int by = 4, size_t cap = 0,
-                     bool last_colour_done = false);
+                     int last_colour_done = 0);
 template <class T>
 void launch_restrict(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                      const DirMapDev& my, const DirMapDev& mz, const T* r, T* rc, hipStream_t s);
@@ -544,7 +552,12 @@ VecJob vec_job(void* p, const void* q, size_t n, const double* scale);
 // Batched (persistent) launches over a work list of jobs
 // h16: every job of W has FP16 stencils (else none has); the batched colour
 // pass, residual and q = -K p run the kernel instance of that format
-template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16);
+// side: the (1,1) pass of the sweep that ends the pre-smoothing, with the jobs'
+// rlast and rside set; launch_side_residual_batched then finishes the (0,1)
+// columns of the jobs of colour (0,1) (rlast set) that ran before it
+template <class T> void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16,
+                                          bool side = false);
+template <class T> void launch_side_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16);
 // batched conjugate gradients (lists of CgJob; residual lists of ColJob with part set)
 unsigned cg_blocks(size_t n);
 template <class T> void launch_dot2_batched(const WorkList& W, hipStream_t s);
@@ -555,7 +568,10 @@ void launch_cg_coeff_batched(const CgJob* jobs, int n, int mode, const int* acti
 void launch_cg_reset_batched(const CgJob* jobs, int n, const int* active, hipStream_t s);
 template <class T> void launch_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16);
 // FusedJob work items: colour J0 then J1 of one row per block (as gs_fused_kernel)
-template <class T> void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16);
+// side: the odd-row launch of the sweep that ends the pre-smoothing, with the
+// jobs' rlast and rside set (gs_fused_kernel with SIDE)
+template <class T> void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16,
+                                                bool side = false);
 template <class T> void launch_restrict_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_prolong_batched(const WorkList& W, hipStream_t s);
 template <class T> void launch_coarse_batched(const WorkList& W, int max_n, hipStream_t s);

@@ -182,12 +182,23 @@ __device__ __forceinline__ void zero_column_r(const ColJob& J, int i, int j) {
 // couples to it (neighbour columns are other colours, all done before), so its
 // final residual is -a_k(above) (x_{k+1,new} - x_{k+1,old}), and the top free
 // node's is zero.  The residual kernel then skips these columns.
-template <class T, bool REV, int SF = 0>
+//
+// SIDE (the forward (1,1) pass that ends a sweep, run in the same launch as
+// the (0,1) pass of its row): the only later changes to the residual of the
+// (0,1) columns (i - 1, j) and (i + 1, j) beside this one are this column's
+// own updates, on the planes k - 1, k, k + 1 around each of their nodes k.
+// Their sums of a (x_new - x_old), with a this node's coupling to that
+// neighbour (K is symmetric, so it is the neighbour's coupling to this node),
+// in the stencil's units, go to row j - 1 of J.rside, which the launch does
+// not otherwise use: the left neighbour's at column i - 1, the right one's at
+// column i.  side_residual then finishes those columns' residual.
+template <class T, bool REV, int SF = 0, bool SIDE = false>
 __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
   const T* __restrict__ f = static_cast<const T*>(J.f);
   T* __restrict__ x = static_cast<T*>(J.x);
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
   T* __restrict__ rl = REV ? nullptr : static_cast<T*>(J.rlast);
+  T* __restrict__ rs = (SIDE && !REV) ? static_cast<T*>(J.rside) : nullptr;
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
     if (rl) zero_column_r<T>(J, i, j);
     return;
@@ -206,6 +217,10 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
     for (int k = kl; k < NZ; ++k) rl[(size_t)k * plane + cols[4]] = T(0);
   }
   T a_up = T(0);  // the coupling of the node below to this one
+  // SIDE: row j - 1 slots of the side sums, and the sums still open for the
+  // planes k - 1 and k (left, right)
+  const int sl_at = (j - 1) * NX + sx(i - 1, NXe), sr_at = (j - 1) * NX + s0;
+  T pl0 = T(0), pl1 = T(0), pr0 = T(0), pr1 = T(0);
   // the forward march carries the node below's upward coupling, the a[4] of
   // the next node (the bottom free node's comes from the plane under it)
   T below = (!REV && kf > 0) ? up_coupling<T, SF>(J, L.node(i, j, kf - 1)) : T(0);
@@ -246,6 +261,21 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
       if (t > 0) rl[(size_t)(k - 1) * plane + cols[4]] = scaled<SF>(-a_up * (xnew - x0[4]), J.sc);
       a_up = a[22];
     }
+    if (SIDE && !REV) {
+      // plane k - 1 is complete with this node's term (its couplings o = 3
+      // and 5 reach the plane below); plane k + 1 opens with o = 21 and 23
+      const T d = xnew - x0[4];
+      pl0 += a[3] * d;
+      pr0 += a[5] * d;
+      if (t > 0) {
+        rs[(size_t)(k - 1) * plane + sl_at] = pl0;
+        rs[(size_t)(k - 1) * plane + sr_at] = pr0;
+      }
+      pl0 = pl1 + a[12] * d;
+      pr0 = pr1 + a[14] * d;
+      pl1 = a[21] * d;
+      pr1 = a[23] * d;
+    }
     x[(size_t)k * plane + cols[4]] = xnew;
     x0[4] = xnew;
 #pragma unroll
@@ -253,6 +283,37 @@ __device__ __forceinline__ void gs_column(const ColJob& J, int i, int j) {
       xl[q] = x0[q];
       x0[q] = xn[q];
     }
+  }
+  if (SIDE && !REV && kl >= kf) {
+    // the top free plane's sums (the plane above it is fixed)
+    rs[(size_t)kl * plane + sl_at] = pl0;
+    rs[(size_t)kl * plane + sr_at] = pr0;
+  }
+}
+
+// The residual of the (0,1) column (i, j) once the (1,1) pass of its row has
+// run with SIDE: the term its own pass left in r (the update above each node,
+// as for the last colour) minus the side sums the (1,1) columns beside it left
+// in row j - 1, scaled to r's units.  A fixed column's r is zero already; a
+// fixed or absent neighbour column changed nothing.
+template <class T, int SF>
+__device__ __forceinline__ void side_residual(const ColJob& J0, int i, int j) {
+  const int NX = J0.NX, NY = J0.NY;
+  if (J0.fc.x_fixed(i, NX) || J0.fc.y_fixed(j, NY)) return;
+  T* __restrict__ r = static_cast<T*>(J0.rlast);
+  const int NXe = (NX + 1) >> 1;
+  const size_t plane = (size_t)NX * NY;
+  const int own = j * NX + sx(i, NXe);
+  const bool hl = i > 0 && !J0.fc.x_fixed(i - 1, NX);
+  const bool hr = i + 1 < NX && !J0.fc.x_fixed(i + 1, NX);
+  const int al = (j - 1) * NX + sx(i > 0 ? i - 1 : i, NXe), ar = (j - 1) * NX + sx(i, NXe);
+  const int kf = J0.fc.k_first(), kl = J0.fc.k_last(J0.NZ);
+  for (int k = kf; k <= kl; ++k) {
+    const size_t o = (size_t)k * plane;
+    T side = T(0);
+    if (hl) side += r[o + al];
+    if (hr) side += r[o + ar];
+    r[o + own] = r[o + own] - scaled<SF>(side, J0.sc);
   }
 }
 
@@ -365,12 +426,25 @@ __device__ __forceinline__ void smooth_column(const ColJob& J, int i, int j, T* 
 
 // One colour pass: a thread per column (i, j) with i = ci mod 2, j = cj mod 2,
 // tiles of 64 x J.by columns per block.
-template <class T, bool REV = false, bool LINE = false, int SF = 0, bool LDS = false>
+template <class T, bool REV, bool LINE, int SF, bool LDS = false, bool SIDE = false>
 __device__ __forceinline__ void gs_pass_body(const ColJob& J, int b, T* ls = nullptr) {
   const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
   const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
   if (ii >= J.ncx || jj >= J.ncy) return;
-  smooth_column<T, REV, LINE, SF, LDS>(J, 2 * ii + J.ci, 2 * jj + J.cj, ls);
+  if constexpr (SIDE && !LINE && !REV)
+    gs_column<T, false, SF, true>(J, 2 * ii + J.ci, 2 * jj + J.cj);
+  else
+    smooth_column<T, REV, LINE, SF, LDS>(J, 2 * ii + J.ci, 2 * jj + J.cj, ls);
+}
+
+// side_residual over the (0,1) columns of a one-colour job's tiles, after the
+// (1,1) pass with SIDE (the one-colour form of the SIDE fused pass)
+template <class T, int SF>
+__device__ __forceinline__ void side_pass_body(const ColJob& J, int b) {
+  const int ii = (b % J.tiles_x) * BX + (threadIdx.x % BX);
+  const int jj = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
+  if (ii >= J.ncx || jj >= J.ncy) return;
+  side_residual<T, SF>(J, 2 * ii + J.ci, 2 * jj + J.cj);
 }
 
 // Dynamic LDS of the line smoother: 2 values per free plane for each thread.
@@ -392,33 +466,58 @@ __device__ __forceinline__ T* line_slots() {
 // smoother, whose column solve keeps 2 values per free plane and thread in
 // LDS (60 KB for 15 planes in FP32; the FP64 Thomas sweep also needs more
 // than the 128 registers a 1024-thread block leaves per lane).
-template <class T, bool LINE>
-constexpr int fused_threads() { return LINE ? 512 : 1024; }
+// The FP64 pass that also leaves the side sums (SIDE) takes 512 as well: with
+// 1024 threads it would spill more of its 128 registers per lane.
+template <class T, bool LINE, bool SIDE = false>
+constexpr int fused_threads() { return LINE || (SIDE && sizeof(T) == 8) ? 512 : 1024; }
 
-template <class T, bool REV, bool LINE, int SF, bool LDS = false>
-__global__ __launch_bounds__((fused_threads<T, LINE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
+// SIDE (forward point smoother, odd rows, the last pre-smoothing sweep): J0,
+// colour (0,1), and J1, colour (1,1), both write r; after a second barrier
+// the (0,1) columns' residual is finished from J1's side sums.
+template <class T, bool REV, bool LINE, int SF, bool LDS = false, bool SIDE = false>
+__global__ __launch_bounds__((fused_threads<T, LINE, SIDE>())) void gs_fused_kernel(ColJob J0, ColJob J1) {
   const int j = 2 * xcd_remap(blockIdx.x, gridDim.x) + J0.cj;
   T* ls = line_slots<T, LDS>();
   for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
     smooth_column<T, REV, LINE, SF, LDS>(J0, 2 * ii + J0.ci, j, ls);
   __syncthreads();
-  for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
-    smooth_column<T, REV, LINE, SF, LDS>(J1, 2 * ii + J1.ci, j, ls);
+  if constexpr (SIDE) {
+    for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
+      gs_column<T, false, SF, true>(J1, 2 * ii + J1.ci, j);
+    __syncthreads();
+    for (int ii = threadIdx.x; ii < J0.ncx; ii += blockDim.x)
+      side_residual<T, SF>(J0, 2 * ii + J0.ci, j);
+  } else {
+    for (int ii = threadIdx.x; ii < J1.ncx; ii += blockDim.x)
+      smooth_column<T, REV, LINE, SF, LDS>(J1, 2 * ii + J1.ci, j, ls);
+  }
 }
 
-template <class T, bool REV, bool LINE, int SF, bool LDS = false>
+template <class T, bool REV, bool LINE, int SF, bool LDS = false, bool SIDE = false>
 __global__ __launch_bounds__(256) void gs_pass_kernel(ColJob J) {
-  gs_pass_body<T, REV, LINE, SF, LDS>(J, xcd_remap(blockIdx.x, J.nblocks), line_slots<T, LDS>());
+  gs_pass_body<T, REV, LINE, SF, LDS, SIDE>(J, xcd_remap(blockIdx.x, J.nblocks), line_slots<T, LDS>());
 }
 
 template <class T, int SF>
-__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) { gs_pass_body<T, false, false, SF>(J, b); }
+__global__ __launch_bounds__(256) void side_residual_kernel(ColJob J) {
+  side_pass_body<T, SF>(J, xcd_remap(blockIdx.x, J.nblocks));
+}
+
+template <class T, int SF, bool SIDE = false>
+__device__ __forceinline__ void gs_pass_fwd(const ColJob& J, int b) {
+  gs_pass_body<T, false, false, SF, false, SIDE>(J, b);
+}
 template <class T, int SF>
 __device__ __forceinline__ void gs_pass_rev(const ColJob& J, int b) { gs_pass_body<T, true, false, SF>(J, b); }
 
-template <class T, int SF>
+template <class T, int SF, bool SIDE = false>
 __global__ __launch_bounds__(256) void gs_pass_batched(WorkList W) {
-  MCW_BATCHED_LOOP(ColJob, (gs_pass_fwd<T, SF>))
+  MCW_BATCHED_LOOP(ColJob, (gs_pass_fwd<T, SF, SIDE>))
+}
+
+template <class T, int SF>
+__global__ __launch_bounds__(256) void side_residual_batched(WorkList W) {
+  MCW_BATCHED_LOOP(ColJob, (side_pass_body<T, SF>))
 }
 
 template <class T, int SF>
@@ -430,19 +529,25 @@ __global__ __launch_bounds__(256) void gs_pass_batched_rev(WorkList W) {
 // gs_fused_kernel runs a row (colour J0, block barrier, colour J1), with
 // blocks of 256 threads looping over the row's columns.  Every thread of a
 // block walks the same work items, so the barrier is reached uniformly.
-template <class T, bool REV, int SF>
+// With SIDE, as gs_fused_kernel with SIDE (a second barrier per work item).
+template <class T, bool REV, int SF, bool SIDE = false>
 __device__ __forceinline__ void gs_fused_item(const FusedJob& F, int b) {
   const int j = 2 * b + F.J0.cj;
   for (int ii = threadIdx.x; ii < F.J0.ncx; ii += blockDim.x)
     gs_column<T, REV, SF>(F.J0, 2 * ii + F.J0.ci, j);
   __syncthreads();
   for (int ii = threadIdx.x; ii < F.J1.ncx; ii += blockDim.x)
-    gs_column<T, REV, SF>(F.J1, 2 * ii + F.J1.ci, j);
+    gs_column<T, REV, SF, SIDE>(F.J1, 2 * ii + F.J1.ci, j);
+  if constexpr (SIDE) {
+    __syncthreads();
+    for (int ii = threadIdx.x; ii < F.J0.ncx; ii += blockDim.x)
+      side_residual<T, SF>(F.J0, 2 * ii + F.J0.ci, j);
+  }
 }
 
-template <class T, bool REV, int SF>
+template <class T, bool REV, int SF, bool SIDE = false>
 __global__ __launch_bounds__(256) void gs_fused_batched(WorkList W) {
-  MCW_BATCHED_LOOP(FusedJob, (gs_fused_item<T, REV, SF>))
+  MCW_BATCHED_LOOP(FusedJob, (gs_fused_item<T, REV, SF, SIDE>))
 }
 
 // ---------------------------------------------------------------- residual
@@ -457,14 +562,15 @@ __device__ __forceinline__ double residual_body(const ColJob& J, int b) {
   const int NX = J.NX, NY = J.NY, NZ = J.NZ;
   // lanes follow the row-split order, so f, r and the stencil are read contiguously
   const int qx = (b % J.tiles_x) * BX + (threadIdx.x % BX);
-  const int j = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
+  const int jr = (b / J.tiles_x) * J.by + (threadIdx.x / BX);
+  const int j = J.skip11 == 2 ? 2 * jr : jr;  // 2: the even rows only
   double acc = 0.0;
   if (qx >= NX || j >= NY) return acc;
   const size_t plane = (size_t)NX * NY;
   const int NXe = (NX + 1) >> 1;
   const int i = qx < NXe ? 2 * qx : 2 * (qx - NXe) + 1;
   const int own = j * NX + qx;
-  if (J.skip11 && (i & j & 1)) return acc;  // written by the sweep's last colour pass
+  if (J.skip11 == 1 && (i & j & 1)) return acc;  // written by the sweep's last colour pass
   if (J.fc.x_fixed(i, NX) || J.fc.y_fixed(j, NY)) {
     for (int k = 0; k < NZ; ++k) r[(size_t)k * plane + own] = T(0);
     return acc;
@@ -1265,6 +1371,15 @@ ColJob col_job(const Dims& d, const Faces& fc, StRef st, const void* f, void* x,
   return J;
 }
 
+void residual_skip(ColJob& J, int mode) {
+  if (mode < 0 || mode > 2) throw Error{MCW_HIP_ERROR, "internal error: residual skip mode"};
+  J.skip11 = mode;
+  if (mode == 2) {
+    J.ncy = (J.NY + 1) / 2;
+    J.nblocks = std::max(0, J.tiles_x * ((J.ncy + J.by - 1) / J.by));
+  }
+}
+
 XferJob xfer_job(const Dims& df, const Dims& dc, const Faces& fc, const DirMapDev& mx,
                  const DirMapDev& my, const DirMapDev& mz, const void* src, void* dst,
                  bool restriction) {
@@ -1316,19 +1431,31 @@ size_t line_lds_bytes(const Dims& d, const Faces& fc, int threads) {
 }
 
 template <class T, bool LINE, int SF>
-void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
-                    hipStream_t s, int by, bool reverse, T* r_last) {
+int smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
+                   hipStream_t s, int by, bool reverse, T* r_last) {
   if (reverse) r_last = nullptr;
   if (by == 0) {
     // colours (0,0),(1,0) then (0,1),(1,1); reversed: (1,1),(0,1) then (1,0),(0,0)
     for (int pr = 0; pr < 2; ++pr) {
       const int c0 = reverse ? 3 - 2 * pr : 2 * pr, c1 = reverse ? c0 - 1 : c0 + 1;
-      const ColJob J0 = col_job(d, fc, st, f, x, cbuf, c0, 1);
+      ColJob J0 = col_job(d, fc, st, f, x, cbuf, c0, 1);
       ColJob J1 = col_job(d, fc, st, f, x, cbuf, c1, 1);
       if (c1 == 3) J1.rlast = r_last;
       if (J0.ncy <= 0) continue;
       const int cols = std::max(J0.ncx, J1.ncx);
       const int threads = std::min(fused_threads<T, LINE>(), std::max(64, (cols + 63) / 64 * 64));
+      if constexpr (!LINE) {
+        if (c1 == 3 && r_last) {
+          // the odd rows of the sweep that ends the pre-smoothing: both colours
+          // leave their residual
+          J0.rlast = r_last;
+          J1.rside = r_last;
+          const int ts = std::min(threads, fused_threads<T, false, true>());
+          gs_fused_kernel<T, false, false, SF, false, true><<<J0.ncy, ts, 0, s>>>(J0, J1);
+          MCW_CHECK_LAUNCH();
+          continue;
+        }
+      }
       if constexpr (LINE) {
         const size_t lds = line_lds_bytes<T>(d, fc, threads);
         if (lds) {
@@ -1346,13 +1473,36 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
         gs_fused_kernel<T, false, LINE, SF><<<J0.ncy, threads, 0, s>>>(J0, J1);
       MCW_CHECK_LAUNCH();
     }
-    return;
+    // every odd row's residual is in place when the point smoother's odd rows
+    // ran with r_last (a level with no odd row has none to compute)
+    return r_last ? (LINE ? 1 : 2) : 0;
   }
   const size_t lds = LINE ? line_lds_bytes<T>(d, fc, BX * by) : 0;
+  ColJob J01{};  // colour (0,1) of the sweep that ends the pre-smoothing
   for (int cc = 0; cc < 4; ++cc) {
     const int c = reverse ? 3 - cc : cc;
     ColJob J = col_job(d, fc, st, f, x, cbuf, c, by);
     if (c == 3) J.rlast = r_last;
+    if constexpr (!LINE) {
+      if (r_last && c == 2) {
+        J.rlast = r_last;
+        J01 = J;
+      }
+      if (r_last && c == 3) {
+        // as the fused pass with SIDE: the (1,1) pass leaves the side sums,
+        // then the (0,1) columns' residual is finished
+        J.rside = r_last;
+        if (J.nblocks > 0) {
+          gs_pass_kernel<T, false, false, SF, false, true><<<J.nblocks, BX * by, 0, s>>>(J);
+          MCW_CHECK_LAUNCH();
+        }
+        if (J01.nblocks > 0) {
+          side_residual_kernel<T, SF><<<J01.nblocks, BX * by, 0, s>>>(J01);
+          MCW_CHECK_LAUNCH();
+        }
+        continue;
+      }
+    }
     if (J.nblocks <= 0) continue;
     if constexpr (LINE) {
       if (lds) {
@@ -1370,28 +1520,24 @@ void smooth_sweep_f(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, 
       gs_pass_kernel<T, false, LINE, SF><<<J.nblocks, BX * by, 0, s>>>(J);
     MCW_CHECK_LAUNCH();
   }
+  return r_last ? (LINE ? 1 : 2) : 0;
 }
 
 // format 1 (FP16 stencil) exists for FP32 V-cycles only
 template <class T, bool LINE>
-void smooth_sweep_t(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
-                    hipStream_t s, int by, bool reverse, T* r_last) {
+int smooth_sweep_t(const Dims& d, const Faces& fc, StRef st, const T* f, T* x, T* cbuf,
+                   hipStream_t s, int by, bool reverse, T* r_last) {
   if constexpr (sizeof(T) == 4) {
-    if (st.h16) {
-      smooth_sweep_f<T, LINE, 1>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
-      return;
-    }
+    if (st.h16) return smooth_sweep_f<T, LINE, 1>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
   }
-  smooth_sweep_f<T, LINE, 0>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
+  return smooth_sweep_f<T, LINE, 0>(d, fc, st, f, x, cbuf, s, by, reverse, r_last);
 }
 
 template <class T>
-void launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
-                         hipStream_t s, int by, bool reverse, T* line_buf, T* r_last) {
-  if (line_buf)
-    smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse, r_last);
-  else
-    smooth_sweep_t<T, false>(d, fc, st, f, x, nullptr, s, by, reverse, r_last);
+int launch_smooth_sweep(const Dims& d, const Faces& fc, StRef st, const T* f, T* x,
+                        hipStream_t s, int by, bool reverse, T* line_buf, T* r_last) {
+  if (line_buf) return smooth_sweep_t<T, true>(d, fc, st, f, x, line_buf, s, by, reverse, r_last);
+  return smooth_sweep_t<T, false>(d, fc, st, f, x, nullptr, s, by, reverse, r_last);
 }
 
 // ---- conjugate gradients on level-0 vectors, coefficients kept on the device
@@ -1620,12 +1766,12 @@ void launch_cg_update(T* e, const T* p, T* r, const T* q, double* sc, size_t n, 
 template <class T>
 void launch_residual(const Dims& d, const Faces& fc, StRef st, const T* x, const T* f, T* r,
                      double* partials, size_t* n_part, hipStream_t s, int by, size_t cap,
-                     bool last_colour_done) {
+                     int last_colour_done) {
   ColJob J = col_job(d, fc, st, f, const_cast<T*>(x), r, -1, by);
   // the norm needs every node's residual in this launch
   if (last_colour_done && partials)
     throw Error{MCW_HIP_ERROR, "internal error: a residual norm needs every column's residual"};
-  J.skip11 = last_colour_done ? 1 : 0;
+  residual_skip(J, last_colour_done);
   if (partials) need_partials((size_t)J.nblocks, cap);
   const bool h16 = sizeof(T) == 4 && st.h16;
   if (partials && h16)
@@ -1800,8 +1946,10 @@ void launch_sum_partials(const double* partials, size_t n_part, int width, doubl
 // ---------------------------------------------------------------- batched launches
 
 template <class T, int SF>
-void launch_gs_batched_f(const WorkList& W, hipStream_t s, int by, bool reverse) {
-  if (reverse)
+void launch_gs_batched_f(const WorkList& W, hipStream_t s, int by, bool reverse, bool side) {
+  if (side && !reverse)
+    gs_pass_batched<T, SF, true><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  else if (reverse)
     gs_pass_batched_rev<T, SF><<<batched_grid(W.total), BX * by, 0, s>>>(W);
   else
     gs_pass_batched<T, SF><<<batched_grid(W.total), BX * by, 0, s>>>(W);
@@ -1809,20 +1957,32 @@ void launch_gs_batched_f(const WorkList& W, hipStream_t s, int by, bool reverse)
 }
 
 template <class T>
-void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16) {
+void launch_gs_batched(const WorkList& W, hipStream_t s, int by, bool reverse, bool h16, bool side) {
   if (W.total <= 0) return;
   if constexpr (sizeof(T) == 4) {
     if (h16) {
-      launch_gs_batched_f<T, 1>(W, s, by, reverse);
+      launch_gs_batched_f<T, 1>(W, s, by, reverse, side);
       return;
     }
   }
-  launch_gs_batched_f<T, 0>(W, s, by, reverse);
+  launch_gs_batched_f<T, 0>(W, s, by, reverse, side);
+}
+
+template <class T>
+void launch_side_residual_batched(const WorkList& W, hipStream_t s, int by, bool h16) {
+  if (W.total <= 0) return;
+  if (sizeof(T) == 4 && h16)
+    side_residual_batched<T, 1><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  else
+    side_residual_batched<T, 0><<<batched_grid(W.total), BX * by, 0, s>>>(W);
+  MCW_CHECK_LAUNCH();
 }
 
 template <class T, int SF>
-void launch_gs_fused_batched_f(const WorkList& W, hipStream_t s, bool reverse) {
-  if (reverse)
+void launch_gs_fused_batched_f(const WorkList& W, hipStream_t s, bool reverse, bool side) {
+  if (side && !reverse)
+    gs_fused_batched<T, false, SF, true><<<batched_grid(W.total), 256, 0, s>>>(W);
+  else if (reverse)
     gs_fused_batched<T, true, SF><<<batched_grid(W.total), 256, 0, s>>>(W);
   else
     gs_fused_batched<T, false, SF><<<batched_grid(W.total), 256, 0, s>>>(W);
@@ -1830,15 +1990,15 @@ void launch_gs_fused_batched_f(const WorkList& W, hipStream_t s, bool reverse) {
 }
 
 template <class T>
-void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16) {
+void launch_gs_fused_batched(const WorkList& W, hipStream_t s, bool reverse, bool h16, bool side) {
   if (W.total <= 0) return;
   if constexpr (sizeof(T) == 4) {
     if (h16) {
-      launch_gs_fused_batched_f<T, 1>(W, s, reverse);
+      launch_gs_fused_batched_f<T, 1>(W, s, reverse, side);
       return;
     }
   }
-  launch_gs_fused_batched_f<T, 0>(W, s, reverse);
+  launch_gs_fused_batched_f<T, 0>(W, s, reverse, side);
 }
 
 template <class T>
@@ -1952,8 +2112,8 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
 }
 
 #define MCW_INST(T)                                                                             \
-  template void launch_smooth_sweep<T>(const Dims&, const Faces&, StRef, const T*, T*,          \
-                                       hipStream_t, int, bool, T*, T*);                         \
+  template int launch_smooth_sweep<T>(const Dims&, const Faces&, StRef, const T*, T*,           \
+                                      hipStream_t, int, bool, T*, T*);                          \
   template void launch_cg_beta<T>(const T*, const T*, const T*, size_t, double*, size_t,       \
                                   double*, hipStream_t);                                        \
   template void launch_add<T>(T*, const T*, size_t, hipStream_t);                              \
@@ -1963,7 +2123,7 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_neg_apply_dot<T>(const Dims&, const Faces&, StRef, const T*, T*,         \
                                         double*, size_t, size_t*, hipStream_t, int);            \
   template void launch_residual<T>(const Dims&, const Faces&, StRef, const T*, const T*, T*,    \
-                                   double*, size_t*, hipStream_t, int, size_t, bool);           \
+                                   double*, size_t*, hipStream_t, int, size_t, int);            \
   template void launch_restrict<T>(const Dims&, const Dims&, const Faces&, const DirMapDev&,    \
                                    const DirMapDev&, const DirMapDev&, const T*, T*,            \
                                    hipStream_t);                                                \
@@ -1973,8 +2133,9 @@ void launch_sum_batched(const SumJob* jobs, int n, hipStream_t s) {
   template void launch_coarse_solve<T>(int, const double*, const int*, const T*, T*,            \
                                        hipStream_t);                                            \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                     \
-  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool, bool);            \
-  template void launch_gs_fused_batched<T>(const WorkList&, hipStream_t, bool, bool);           \
+  template void launch_gs_batched<T>(const WorkList&, hipStream_t, int, bool, bool, bool);      \
+  template void launch_side_residual_batched<T>(const WorkList&, hipStream_t, int, bool);       \
+  template void launch_gs_fused_batched<T>(const WorkList&, hipStream_t, bool, bool, bool);     \
   template void launch_residual_batched<T>(const WorkList&, hipStream_t, int, bool);            \
   template void launch_restrict_batched<T>(const WorkList&, hipStream_t);                       \
   template void launch_prolong_batched<T>(const WorkList&, hipStream_t);                        \

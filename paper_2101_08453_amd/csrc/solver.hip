@@ -336,13 +336,15 @@ void vcycle(mcw_handle& h, int l, T* x, const T* f) {
     return;
   }
   const StRef st = stencil_of<T>(L);
-  // the last pre-smoothing sweep leaves the residual of its last colour behind
+  // the last pre-smoothing sweep leaves the residual of the columns whose
+  // residual it knows (its last colour, or every odd row) behind
   const int nu = h.opt.nu_pre;
+  int known = 0;
   for (int s = 0; s < nu; ++s)
-    launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L),
-                           s == nu - 1 ? L.r.as<T>() : nullptr);
+    known = launch_smooth_sweep<T>(L.d, h.faces, st, f, x, h.stream, L.by_gs, false, line_buf<T>(h, L),
+                                   s == nu - 1 ? L.r.as<T>() : nullptr);
   launch_residual<T>(L.d, h.faces, st, x, f, L.r.as<T>(), nullptr, nullptr, h.stream, L.by_res, 0,
-                     nu > 0);
+                     known);
   Level& C = h.levels[l + 1];
   launch_restrict<T>(L.d, C.d, h.faces, L.dmx, L.dmy, L.dmz, L.r.as<T>(), C.f.as<T>(), h.stream);
   launch_fill<T>(C.x.as<T>(), C.d.N(), T(0), h.stream);
@@ -1292,6 +1294,7 @@ class Batch {
     depth_ = 0;
     for (auto* h : hs_) depth_ = std::max(depth_, (int)h->levels.size());
     gs_.assign(depth_, {});
+    gs2r_.assign(depth_, {});
     gs3r_.assign(depth_, {});
     gsf_.assign(depth_, {});
     gsfr_.assign(depth_, {});
@@ -1307,7 +1310,7 @@ class Batch {
     prol_.assign(depth_, {});
     coarse_.assign(depth_, {});
     for (int d = 0; d < depth_; ++d) {
-      std::vector<ColJob> gsj[4], rj, g3r, rvj;
+      std::vector<ColJob> gsj[4], rj, g2r, g3r, rvj;
       std::vector<FusedJob> fj2[2], fr2[2], f3r;
       std::vector<int> fm2[2], frm2[2];
       std::vector<XferJob> rsj, pj;
@@ -1344,10 +1347,18 @@ class Batch {
           if (J.nblocks > 0) {
             gsj[c].push_back(J);
             gsm[c].push_back(i);
+            if (c == 2) {
+              // colour (0,1) of the last pre-smoothing sweep writes the part of its
+              // residual its own updates leave (the rest follows the (1,1) pass)
+              g2r.push_back(J);
+              g2r.back().rlast = r_last ? V.r.p : nullptr;
+            }
             if (c == 3) {
               // the last colour of the last pre-smoothing sweep writes its residual
+              // and the side sums of the (0,1) columns
               g3r.push_back(J);
               g3r.back().rlast = r_last ? V.r.p : nullptr;
+              g3r.back().rside = r_last ? V.r.p : nullptr;
             }
           }
         }
@@ -1362,8 +1373,12 @@ class Batch {
             fj2[pr].push_back(F);
             fm2[pr].push_back(i);
             if (pr == 1) {
+              // the odd rows of the last pre-smoothing sweep leave their residual
+              // (gs_fused_kernel with SIDE)
               f3r.push_back(F);
+              f3r.back().J0.rlast = r_last ? V.r.p : nullptr;
               f3r.back().J1.rlast = r_last ? V.r.p : nullptr;
+              f3r.back().J1.rside = r_last ? V.r.p : nullptr;
             }
           }
           FusedJob R{};
@@ -1377,7 +1392,7 @@ class Batch {
         }
         rj.push_back(col_job(V.d, h.faces, stencil_of<float>(V), V.f.p, V.x.p, V.r.p, -1, by_res_[d]));
         rvj.push_back(rj.back());
-        rvj.back().skip11 = r_last ? 1 : 0;
+        residual_skip(rvj.back(), r_last ? 2 : 0);
         rm.push_back(i);
         rsj.push_back(xfer_job(V.d, C.d, h.faces, V.dmx, V.dmy, V.dmz, V.r.p, C.f.p, true));
         rsm.push_back(i);
@@ -1387,6 +1402,7 @@ class Batch {
         fm.push_back(i);
       }
       for (int c = 0; c < 4; ++c) gs_[d][c] = add_split(gsj[c], gsm[c]);
+      gs2r_[d] = add_split(g2r, gsm[2]);
       gs3r_[d] = add_split(g3r, gsm[3]);
       for (int pr = 0; pr < 2; ++pr) {
         gsf_[d][pr] = add_split(fj2[pr], fm2[pr]);
@@ -1856,15 +1872,21 @@ class Batch {
     for (int s = 0; s < nu_pre; ++s) {
       if (fused_[d]) {
         for (int pr = 0; pr < 2; ++pr) {
-          const ByFormat& g = (pr == 1 && s == nu_pre - 1) ? gsf3r_[d] : gsf_[d][pr];
-          for (int f = 0; f < 2; ++f) launch_gs_fused_batched<float>(fix(g.w[f]), s_, false, f == 1);
+          const bool side = pr == 1 && s == nu_pre - 1;
+          const ByFormat& g = side ? gsf3r_[d] : gsf_[d][pr];
+          for (int f = 0; f < 2; ++f) launch_gs_fused_batched<float>(fix(g.w[f]), s_, false, f == 1, side);
         }
         continue;
       }
+      const bool last = s == nu_pre - 1;
       for (int c = 0; c < 4; ++c) {
-        const ByFormat& g = (c == 3 && s == nu_pre - 1) ? gs3r_[d] : gs_[d][c];
-        for (int f = 0; f < 2; ++f) launch_gs_batched<float>(fix(g.w[f]), s_, by_gs_[d], false, f == 1);
+        const ByFormat& g = last && c == 2 ? gs2r_[d] : (last && c == 3 ? gs3r_[d] : gs_[d][c]);
+        for (int f = 0; f < 2; ++f)
+          launch_gs_batched<float>(fix(g.w[f]), s_, by_gs_[d], false, f == 1, last && c == 3);
       }
+      if (last)
+        for (int f = 0; f < 2; ++f)
+          launch_side_residual_batched<float>(fix(gs2r_[d].w[f]), s_, by_gs_[d], f == 1);
     }
     // with pre-smoothing, the last colour's residual is already in place
     for (int f = 0; f < 2; ++f) launch_residual_batched<float>(fix(resv_[d].w[f]), s_, by_res_[d], f == 1);
@@ -1996,7 +2018,8 @@ class Batch {
   size_t cg_slot_ = 0, cgtab_off_ = 0;
   int depth_ = 0, max_coarse_ = 0;
   std::vector<std::array<ByFormat, 4>> gs_;
-  std::vector<ByFormat> gs3r_;  // colour (1,1) writing r: the last pre-smoothing pass
+  std::vector<ByFormat> gs2r_;  // colour (0,1) writing its part of r: the last pre-smoothing sweep
+  std::vector<ByFormat> gs3r_;  // colour (1,1) writing r and the side sums: the last pre-smoothing pass
   // two-colour passes (forward pairs, reversed pairs, the last pre-smoothing
   // pair writing r), used at the depths where fused_ is set
   std::vector<std::array<ByFormat, 2>> gsf_, gsfr_;
