@@ -308,12 +308,25 @@ __device__ __forceinline__ void side_residual(const ColJob& J0, int i, int j) {
   const bool hr = i + 1 < NX && !J0.fc.x_fixed(i + 1, NX);
   const int al = (j - 1) * NX + sx(i > 0 ? i - 1 : i, NXe), ar = (j - 1) * NX + sx(i, NXe);
   const int kf = J0.fc.k_first(), kl = J0.fc.k_last(J0.NZ);
-  for (int k = kf; k <= kl; ++k) {
-    const size_t o = (size_t)k * plane;
-    T side = T(0);
-    if (hl) side += r[o + al];
-    if (hr) side += r[o + ar];
-    r[o + own] = r[o + own] - scaled<SF>(side, J0.sc);
+  // eight planes at a time, their loads issued together (clamped to the top
+  // free plane, so every load is in range and unconditional); an absent
+  // neighbour's sum is taken as zero, which adds exactly nothing
+  constexpr int CH = 8;
+  for (int k0 = kf; k0 <= kl; k0 += CH) {
+    T v[CH], sl[CH], sr[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const size_t o = (size_t)min(k0 + c, kl) * plane;
+      v[c] = r[o + own];
+      sl[c] = r[o + al];
+      sr[c] = r[o + ar];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (k0 + c > kl) break;
+      const T side = (hl ? sl[c] : T(0)) + (hr ? sr[c] : T(0));
+      r[(size_t)(k0 + c) * plane + own] = v[c] - scaled<SF>(side, J0.sc);
+    }
   }
 }
 
