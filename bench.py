@@ -298,8 +298,8 @@ def bench_c4(args):
         ms_res, _ = mcwind.run_kernel_batch(g32, "residual", 16)
         b_sweep = (ST32_BYTES + 12.0) * n_free
         b_res = (ST32_BYTES + 12.0) * sum(p.n_nodes for p in probs)
-        kname = ("gs_fused_batched<float, false, 0> (two colour passes per launch)" if lps == 2
-                 else "gs_pass_batched<float, 0> (one colour pass per launch)")
+        kname = ("gs_fused_batched<float, false, 0, false> (two colour passes per launch)" if lps == 2
+                 else "gs_pass_batched<float, 0, false> (one colour pass per launch)")
         batch_roof = {"bound": "hbm", "kernel": kname, "launches_per_sweep": lps,
                       "bytes_per_launch": b_sweep / lps, "ms_per_launch": round(ms_sweep / lps, 4),
                       "achieved": round(b_sweep / ms_sweep / 1e6, 1), "peak": HBM_PEAK_GBS,
@@ -735,7 +735,7 @@ def main():
                 "traffic": counted_traffic(),
                 "copy_GB/s": round(kernels["device_copy"]["GB/s"], 1),
                 "frac_of_copy": round(achieved / kernels["device_copy"]["GB/s"], 4),
-                "kernel": ("gs_fused_kernel<float, false, false, 0, false> (fine-grid colour passes, two per launch)"
+                "kernel": ("gs_fused_kernel<float, false, false, 0, false, false> (fine-grid colour passes, two per launch)"
                            if k["launches_per_sweep"] == 2 else
                            "gs_pass_kernel<float, false, false, 0, false> (fine-grid colour pass)"),
                 "bytes_per_launch": k["bytes"], "ms_per_launch": round(k["ms"], 4)}
