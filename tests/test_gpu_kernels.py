@@ -198,6 +198,34 @@ def test_vcycle_matches_oracle_vcycle(name):
     assert gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref) < 1e-10
 
 
+@pytest.mark.parametrize("shape", [0, 1, 4])
+def test_vcycle_matches_oracle_with_every_pass_shape(shape, tmp_path, monkeypatch):
+    """The last pre-smoothing sweep leaves the odd rows' residual both in the
+    two-colour launch (shape 0) and after the one-colour passes (1 or 4 rows of
+    64 columns per block).  On a 130x100x6 hills grid whose fine level (92 K
+    nodes) is forced to each shape through the tuning cache, one FP64 V-cycle
+    against the oracle's."""
+    from paper_2101_08453_amd import inputs, mcwind
+    p = inputs.hills_problem(130, 100, 6, 3, 7, a=(1.0, 1.0, 3.0))
+    shp = f"{p.dims[0] + 1}x{p.dims[1] + 1}x{p.dims[2] + 1}"
+    cache = tmp_path / "tune.json"
+    cache.write_text('{\n  "gfx950|gsf|%s|f64": %d,\n  "gfx950|res|%s|f64": 4\n}\n' % (shp, shape, shp))
+    monkeypatch.setenv("MCW_TUNE_CACHE", str(cache))
+    print(f"[case] V-cycle, fine pass shape {shape}", flush=True)
+    g, _ = mcwind.grid_from_problem(p, precision="fp64", coarse_direct_max=60)
+    assert g.tile_rows(0)[0] == shape
+    levels = mg.build_hierarchy(p.X, p.Y, p.Z, p.a, p.gamma, coarse_max=60)
+    assert [lv.dims for lv in levels] == [tuple(int(v) - 1 for v in g.level_shape(l)[::-1])
+                                          for l in range(g.num_levels())]
+    M = mg.Multigrid(levels)
+    L = levels[0]
+    x, f, _ = _level_vectors(p, L, 23)
+    xg = _dev(x)
+    g.vcycle(xg, _dev(f))
+    ref = M.vcycle(x.ravel()[L.free], f.ravel()[L.free])
+    assert gc.rel_err(xg.cpu().numpy().ravel()[L.free], ref) < 1e-10
+
+
 @pytest.mark.parametrize("nu", [(0, 2), (1, 1), (3, 2)])
 @pytest.mark.parametrize("smoother", ["point", "line"])
 @pytest.mark.parametrize("name", ["ragged", "tiles"])
