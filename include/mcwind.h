@@ -373,7 +373,11 @@ mcw_status mcw_coarse_solve(mcw_handle* h, const void* r, void* e);
 
 /* One V-cycle on level 0 with x in/out, f in (V-cycle precision): smoothing,
  * the coarse-grid correction of eqs. (6)-(7) applied recursively, smoothing
- * (Sec. 3). */
+ * (Sec. 3).  The residual that is restricted is f - K x after the
+ * pre-smoothing; where the last pre-smoothing sweep already knows it (the odd
+ * rows with the point smoother, the (1,1) columns with the line smoother) it
+ * is formed from that sweep's updates, which differs from computing f - K x
+ * only by rounding. */
 mcw_status mcw_vcycle(mcw_handle* h, void* x, const void* f);
 
 /* Run `reps` launches of one multigrid kernel on level l's own buffers (their
